@@ -1,0 +1,150 @@
+/*
+ * nslct.h -- C ABI of the MI355X (gfx950) 2D nonseparable discrete linear
+ * canonical transform by the CM-CC-CM-CC decomposition of Pei & Huang,
+ * "Two-dimensional nonseparable discrete linear canonical transform based on
+ * CM-CC-CM-CC decomposition".
+ *
+ * What is computed
+ *   For a 4x4 ABCD matrix M = (A, B; C, D) with M J M^T = J (Sec. 1,
+ *   eq. Intro12) the forward transform is the high-accuracy NsDLCT
+ *     type 1 (CM-CC-CM-CC, Sec. 4.2.1, eq. HA28):
+ *       G = CM(P1) CC(B') CM(P3) CC(H) g
+ *     type 2 (CC-CM-CC-CM, Sec. 4.3, eq. CCCMCCCM40):
+ *       G = CC(H1) CM(Q1) CC(B1') CM(Q3) g
+ *   with the discrete chirp multiplication CM (Sec. 2.1, eq. BasicCM12) and
+ *   chirp convolution CC(B) = F^-1 CM(-B) F (Sec. 2.3, eq. BasicCC20), the DFTs
+ *   carrying the constants of eqs. BasicDFT16/20.  The type follows the sign of
+ *   tr B (Sec. 4.4, eq. Reversible08) unless overridden; the gauge H (H1) is
+ *   the minimiser of the phase-space growth product of eq. HA24.
+ *   The chain equals a unitary operator L; nslct_inverse applies L^H = L^-1,
+ *   the reversed chain with negated stage matrices (eq. CCCMCCCM30).
+ *
+ * Data layout (all entry points)
+ *   An image is Nx*Ny interleaved complex numbers (re, im), row-major
+ *   [Nx][Ny]: element [m][n] holds g(x_m, y_n) with n contiguous.  Sample
+ *   indices are centred: x_m = (m - floor(Nx/2)) * dx, y_n = (n - floor(Ny/2)) * dy.
+ *   Output uses the same grid (spacings dx, dy), as in the paper's
+ *   experiments.  Precision NSLCT_C64 uses float (8 bytes per sample),
+ *   NSLCT_C128 uses double (16 bytes per sample).
+ *
+ * Ownership and errors
+ *   Device pointers are owned by the caller and must be 16-byte aligned
+ *   device memory on the current HIP device.  `stream` is a hipStream_t
+ *   (0 = the legacy default stream).  A plan is immutable after creation,
+ *   holds no device memory and may be used from several threads and streams
+ *   at once.  Every entry point returns NSLCT_OK (0) or a negative code;
+ *   on error no device work has been queued and nslct_last_error() returns
+ *   a message (per thread).  Launches are asynchronous: a fault inside a
+ *   kernel shows up at the next synchronising HIP call.
+ *
+ * Sizes
+ *   Nx, Ny are powers of two from 2 to 4096 (NSLCT_E_SIZE otherwise).
+ */
+#ifndef NSLCT_H
+#define NSLCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define NSLCT_OK 0
+#define NSLCT_E_ARG (-1)              /* null / misaligned pointer, bad scalar */
+#define NSLCT_E_NOT_SYMPLECTIC (-2)   /* max|M J M^T - J| above the tolerance */
+#define NSLCT_E_NO_DECOMPOSITION (-3) /* no symmetric gauge with invertible B' */
+#define NSLCT_E_SIZE (-4)             /* unsupported Nx, Ny */
+#define NSLCT_E_HIP (-5)              /* HIP runtime error (message kept) */
+#define NSLCT_E_UNSUPPORTED (-6)      /* valid request this build does not do */
+
+/* Precision of storage and arithmetic. */
+#define NSLCT_C64 0  /* complex64 storage, FP32 butterflies, FP64-exact phases */
+#define NSLCT_C128 1 /* complex128 storage and arithmetic */
+
+typedef struct nslct_plan_s* nslct_plan_t;
+
+/* Planning options; initialise with nslct_opts_default. */
+typedef struct {
+    int precision;         /* NSLCT_C64 (default) or NSLCT_C128 */
+    int type_override;     /* 0: trace rule (eq. Reversible08), 1: CM-CC-CM-CC, 2: CC-CM-CC-CM */
+    double symplectic_tol; /* accepted max|M J M^T - J|, default 1e-9 */
+} nslct_opts;
+
+/* Stage description of a plan (and input of nslct_plan_from_stages).
+ *   type 1: mats = {P1, B', P3, H}    -> CM(P1) CC(B') CM(P3) CC(H)
+ *   type 2: mats = {H1, Q1, B1', Q3}  -> CC(H1) CM(Q1) CC(B1') CM(Q3)
+ *   type 0: mats[0] = C (pure chirp multiplication, B = 0, A = D = I)
+ * Each symmetric 2x2 matrix is stored as (x11, x12, x22). */
+typedef struct {
+    int type;
+    double mats[4][3];
+    double h[3];               /* gauge (h11, h12, h22), zero for type 0 */
+    double gauge_objective;    /* value of the eq. HA24 product at h */
+    double symplectic_residual;/* max|M J M^T - J| of the planned matrix */
+    double dx, dy;             /* space sampling intervals */
+    double dwx, dwy;           /* frequency intervals 2 pi / (N dx), 2 pi / (N dy) */
+} nslct_stages;
+
+/* Fills *opts with the defaults. */
+void nslct_opts_default(nslct_opts* opts);
+
+/* Plans the transform of an Nx x Ny image for ABCD matrix `abcd` (16 doubles,
+ * row-major 4x4) with sampling intervals dx, dy > 0 (host only, FP64).
+ * Validates M (eq. Intro12), picks the type (eq. Reversible08) and solves the
+ * gauge problem of eq. HA24.  B = 0 with A = D = I gives a pure CM; B = 0
+ * otherwise is an affine map (eq. Intro20): NSLCT_E_NO_DECOMPOSITION. */
+int nslct_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, nslct_plan_t* out);
+int nslct_plan_ex(const double abcd[16], int Nx, int Ny, double dx, double dy,
+                  const nslct_opts* opts, nslct_plan_t* out);
+
+/* Plans from explicit stage matrices (type and mats read from *st; dx, dy
+ * read from *st; other fields ignored).  Used to run the chain at fixed
+ * stages (Secs. 4.2-4.3). */
+int nslct_plan_from_stages(const nslct_stages* st, int Nx, int Ny, const nslct_opts* opts,
+                           nslct_plan_t* out);
+
+/* Copies the plan's stage description into *out. */
+int nslct_plan_get_stages(nslct_plan_t plan, nslct_stages* out);
+
+/* Phase-space growth check of the plan (Sec. 4.2.1, eqs. HA12-HA20): the box
+ * |x|,|y| <= frac*N*d/2, |w| <= frac*pi/d pushed through the four stages in
+ * application order stays inside the grid.  Host only.  *ok = 1 or 0. */
+int nslct_plan_box_check(nslct_plan_t plan, double frac, int* ok);
+
+void nslct_plan_destroy(nslct_plan_t plan);
+
+/* Forward transform of one image; in == out (in place) is allowed. */
+int nslct_forward(nslct_plan_t plan, const void* in, void* out, void* stream);
+
+/* Inverse (= adjoint) transform, eq. CCCMCCCM30; in == out allowed. */
+int nslct_inverse(nslct_plan_t plan, const void* in, void* out, void* stream);
+
+/* `count` images of the plan's shape stored back to back (image stride
+ * Nx*Ny samples), all with the plan's matrix.  in == out allowed. */
+int nslct_forward_many(nslct_plan_t plan, int count, const void* in, void* out, void* stream);
+int nslct_inverse_many(nslct_plan_t plan, int count, const void* in, void* out, void* stream);
+
+/* One of the five fused passes of the forward (direction 0) or inverse
+ * (direction 1) chain, pass = 0..4, on `count` images: pass 0 reads `in`,
+ * every pass writes `out`; chaining passes 0..4 with in = out after the first
+ * equals nslct_forward_many / nslct_inverse_many.  For profiling. */
+int nslct_launch_pass(nslct_plan_t plan, int direction, int pass, int count,
+                      const void* in, void* out, void* stream);
+
+/* Plain device-to-device copy kernel of `bytes` bytes (multiple of 16): the
+ * bandwidth reference the transform is measured against. */
+int nslct_device_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* nslct_last_error(void);
+const char* nslct_strerror(int code);
+
+/* Library version string. */
+const char* nslct_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSLCT_H */

@@ -1,0 +1,150 @@
+"""MI355X-native 2D nonseparable discrete LCT (CM-CC-CM-CC decomposition).
+
+Thin Python binding of ``libnslct.so`` (C ABI in ``include/nslct.h``).  The
+binding only marshals arguments: every step of the transform runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the current HIP
+stream.  There is no fallback: if the library is missing or fails to load,
+importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import (NSLCT_C64, NSLCT_C128, NslctError, Stages, lib, check)  # noqa: F401
+
+__all__ = ["Plan", "NslctError", "lib", "device_copy", "NSLCT_C64", "NSLCT_C128"]
+
+_PRECISION = {"c64": NSLCT_C64, "c128": NSLCT_C128}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None) -> int:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """A planned transform for one ABCD matrix and grid.
+
+    Mirrors ``nslct_plan_ex`` / ``nslct_plan_from_stages``; ``forward`` and
+    ``inverse`` run on torch tensors of shape [..., Nx, Ny] (complex64 for
+    precision "c64", complex128 for "c128") resident on the current device.
+    """
+
+    def __init__(self, abcd=None, Nx: int = 0, Ny: int = 0, dx: float = 1.0, dy: float = 1.0,
+                 precision: str = "c64", type_override: int = 0, symplectic_tol: float = 1e-9,
+                 _handle=None):
+        self.precision = precision
+        if _handle is not None:
+            self._h = _handle
+        else:
+            opts = lib.opts()
+            opts.precision = _PRECISION[precision]
+            opts.type_override = int(type_override)
+            opts.symplectic_tol = float(symplectic_tol)
+            m = np.ascontiguousarray(np.asarray(abcd, dtype=np.float64).reshape(16))
+            h = ctypes.c_void_p()
+            check(lib.nslct_plan_ex(m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(Nx), int(Ny),
+                                    float(dx), float(dy), ctypes.byref(opts), ctypes.byref(h)))
+            self._h = h
+        self.Nx, self.Ny = int(Nx), int(Ny)
+
+    @classmethod
+    def from_stages(cls, typ: int, mats, Nx: int, Ny: int, dx: float, dy: float,
+                    precision: str = "c64") -> "Plan":
+        st = Stages()
+        st.type = int(typ)
+        for i, X in enumerate(mats):
+            X = np.asarray(X, dtype=np.float64)
+            st.mats[i][0] = X[0, 0]
+            st.mats[i][1] = 0.5 * (X[0, 1] + X[1, 0])
+            st.mats[i][2] = X[1, 1]
+        st.dx, st.dy = float(dx), float(dy)
+        opts = lib.opts()
+        opts.precision = _PRECISION[precision]
+        h = ctypes.c_void_p()
+        check(lib.nslct_plan_from_stages(ctypes.byref(st), int(Nx), int(Ny), ctypes.byref(opts),
+                                         ctypes.byref(h)))
+        p = cls.__new__(cls)
+        p.precision = precision
+        p._h = h
+        p.Nx, p.Ny = int(Nx), int(Ny)
+        return p
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            lib.nslct_plan_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------------ info
+    def stages(self) -> dict:
+        st = Stages()
+        check(lib.nslct_plan_get_stages(self._h, ctypes.byref(st)))
+        mats = []
+        for i in range(4):
+            a, b, c = st.mats[i][0], st.mats[i][1], st.mats[i][2]
+            mats.append(np.array([[a, b], [b, c]]))
+        return {"type": st.type, "mats": mats, "h": np.array(list(st.h)),
+                "f": st.gauge_objective, "residual": st.symplectic_residual,
+                "dx": st.dx, "dy": st.dy, "dwx": st.dwx, "dwy": st.dwy,
+                "Nx": getattr(self, "Nx", None), "Ny": getattr(self, "Ny", None)}
+
+    def box_check(self, frac: float = 0.5) -> bool:
+        ok = ctypes.c_int()
+        check(lib.nslct_plan_box_check(self._h, float(frac), ctypes.byref(ok)))
+        return bool(ok.value)
+
+    # ------------------------------------------------------------- transforms
+    def _check_tensor(self, x):
+        torch = _torch()
+        want = torch.complex64 if self.precision == "c64" else torch.complex128
+        if x.dtype != want:
+            raise TypeError(f"expected {want}, got {x.dtype}")
+        if not x.is_cuda:
+            raise TypeError("tensor must be on the GPU")
+        if tuple(x.shape[-2:]) != (self.Nx, self.Ny):
+            raise ValueError(f"expected [..., {self.Nx}, {self.Ny}], got {tuple(x.shape)}")
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.numel() // (self.Nx * self.Ny)
+
+    def _run(self, fn, x, out, stream):
+        count = self._check_tensor(x)
+        if out is None:
+            out = _torch().empty_like(x)
+        else:
+            self._check_tensor(out)
+            if out.shape != x.shape:
+                raise ValueError("out must have the shape of x")
+        check(fn(self._h, count, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                 ctypes.c_void_p(_stream_ptr(stream))))
+        return out
+
+    def forward(self, x, out=None, stream=None):
+        return self._run(lib.nslct_forward_many, x, out, stream)
+
+    def inverse(self, x, out=None, stream=None):
+        return self._run(lib.nslct_inverse_many, x, out, stream)
+
+    def launch_pass(self, direction: int, pass_: int, x, out, stream=None):
+        count = self._check_tensor(x)
+        check(lib.nslct_launch_pass(self._h, int(direction), int(pass_), int(count),
+                                    ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(_stream_ptr(stream))))
+        return out
+
+
+def device_copy(src, dst, stream=None):
+    """Plain copy kernel (bandwidth reference)."""
+    nbytes = src.numel() * src.element_size()
+    check(lib.nslct_device_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream_ptr(stream))))
+    return dst

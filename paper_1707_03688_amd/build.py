@@ -1,0 +1,69 @@
+"""Builds libnslct.so (HIP kernels for gfx950 + host planner + C ABI) in-tree.
+
+    python -m paper_1707_03688_amd.build        # or build() from Python
+
+Every call recompiles.  Packed FP32 instructions are disabled for all device
+code (``-packed-fp32-ops``).
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(PKG, "libnslct.so")
+
+ARCH = os.environ.get("NSLCT_OFFLOAD_ARCH", "gfx950")
+
+HIPCC_FLAGS = [
+    "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+]
+
+
+def _hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found (ROCm is required to build the HIP library)")
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError(f"build step failed ({r.returncode}): {' '.join(cmd)}")
+    if verbose and (r.stdout or r.stderr):
+        errs = [l for l in (r.stdout + r.stderr).splitlines()
+                if "packed-fp32-ops" not in l and l.strip()]
+        if errs:
+            print("\n".join(errs), flush=True)
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = _hipcc()
+    out_dir = os.path.join(PKG, "_build")
+    os.makedirs(out_dir, exist_ok=True)
+    inc = [f"-I{INCLUDE}", f"-I{CSRC}"]
+    objs = []
+    for src in ("planner.cpp", "nslct.hip"):
+        obj = os.path.join(out_dir, src.replace(".", "_") + ".o")
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        _run([hipcc, *HIPCC_FLAGS, *inc, *lang, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    _run([hipcc, *HIPCC_FLAGS, "-shared", *objs, "-o", tmp], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

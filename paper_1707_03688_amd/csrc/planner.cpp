@@ -1,0 +1,635 @@
+// Host planner of the 2D HA-NsDLCT (FP64).
+//
+// Steps (Pei & Huang, CM-CC-CM-CC NsDLCT):
+//   1. M J M^T = J within tolerance (Sec. 1, eq. Intro12).
+//   2. B = 0: a pure chirp multiplication when A = D = I (eq. BasicCM12);
+//      otherwise an affine map (eq. Intro20), which is rejected.
+//   3. Type from the sign of tr B (Sec. 4.4, eq. Reversible08), tr B = 0 read
+//      as type 1; a type whose gauge equation has no solution falls back to
+//      the other type.
+//   4. Gauge: minimise the product of the growth ratios gamma (eq. HA16) of
+//      the four stage matrices (eq. HA24) over symmetric H with B' = B - A H
+//      symmetric (type 1, eq. Bnonsym32) or B1' = B - H1 D symmetric (type 2,
+//      eq. CCCMCCCM08), |det B'| >= 1e-6 max(1, max|B_ij|^2).  The feasible
+//      set is a plane (or all of Sym(2)); the objective is piecewise smooth
+//      with minima on |.| kinks, so the search is exhaustive on a grid, then
+//      Nelder-Mead, then Newton "snapping" onto the kinks.  Ties within
+//      relative 1e-9 go to the smallest ||H||_F, then lexicographic order.
+//   5. Stage matrices (type 1: P1 = (D'-I)B'^-1, B', P3 = B'^-1(A-I), H,
+//      eq. Bnonsym12; type 2: H1, Q1 = (D-I)B1'^-1, B1', Q3 = B1'^-1(A1'-I),
+//      eq. CCCMCCCM16), symmetrised, then the five-slot chain and its adjoint
+//      (eq. CCCMCCCM30) with phase coefficients in fixed-point turns.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+namespace nslct {
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+struct M2 {
+    double a11, a12, a21, a22;
+};
+
+M2 mul(const M2& x, const M2& y) {
+    return {x.a11 * y.a11 + x.a12 * y.a21, x.a11 * y.a12 + x.a12 * y.a22,
+            x.a21 * y.a11 + x.a22 * y.a21, x.a21 * y.a12 + x.a22 * y.a22};
+}
+M2 sub(const M2& x, const M2& y) { return {x.a11 - y.a11, x.a12 - y.a12, x.a21 - y.a21, x.a22 - y.a22}; }
+M2 minus_eye(const M2& x) { return {x.a11 - 1.0, x.a12, x.a21, x.a22 - 1.0}; }
+double det(const M2& x) { return x.a11 * x.a22 - x.a12 * x.a21; }
+
+struct Blocks {
+    M2 A, B, C, D;
+};
+
+Blocks split(const double m[16]) {
+    auto at = [&](int r, int c) { return m[4 * r + c]; };
+    return {{at(0, 0), at(0, 1), at(1, 0), at(1, 1)},
+            {at(0, 2), at(0, 3), at(1, 2), at(1, 3)},
+            {at(2, 0), at(2, 1), at(3, 0), at(3, 1)},
+            {at(2, 2), at(2, 3), at(3, 2), at(3, 3)}};
+}
+
+double symplectic_residual(const double m[16]) {
+    // max |M J M^T - J| with J = (0, I; -I, 0).
+    double J[16] = {0, 0, 1, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, -1, 0, 0};
+    double MJ[16], R = 0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double s = 0;
+            for (int k = 0; k < 4; ++k) s += m[4 * i + k] * J[4 * k + j];
+            MJ[4 * i + j] = s;
+        }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double s = 0;
+            for (int k = 0; k < 4; ++k) s += MJ[4 * i + k] * m[4 * j + k];
+            R = std::max(R, std::fabs(s - J[4 * i + j]));
+        }
+    return R;
+}
+
+void sym3(const M2& x, double out[3]) {
+    out[0] = x.a11;
+    out[1] = 0.5 * (x.a12 + x.a21);
+    out[2] = x.a22;
+}
+
+// The decomposition of one matrix for one type, evaluated at gauge h.
+struct Gauge {
+    Blocks b;
+    int type;
+    double dmin;
+
+    // Stage matrices in formula order (leftmost first), symmetrised.
+    bool stages(const double h[3], double out[4][3], double* dt) const {
+        const M2 H{h[0], h[1], h[1], h[2]};
+        M2 Bp, X1, X3;
+        if (type == 1) {
+            Bp = sub(b.B, mul(b.A, H));
+            const M2 Dp = sub(b.D, mul(b.C, H));
+            *dt = det(Bp);
+            if (!(std::fabs(*dt) >= dmin)) return false;
+            const M2 Bi{Bp.a22 / *dt, -Bp.a12 / *dt, -Bp.a21 / *dt, Bp.a11 / *dt};
+            X1 = mul(minus_eye(Dp), Bi);   // P1 = (D' - I) B'^-1
+            X3 = mul(Bi, minus_eye(b.A));  // P3 = B'^-1 (A - I)
+            sym3(X1, out[0]);
+            sym3(Bp, out[1]);
+            sym3(X3, out[2]);
+            sym3(H, out[3]);
+        } else {
+            Bp = sub(b.B, mul(H, b.D));
+            const M2 Ap = sub(b.A, mul(H, b.C));
+            *dt = det(Bp);
+            if (!(std::fabs(*dt) >= dmin)) return false;
+            const M2 Bi{Bp.a22 / *dt, -Bp.a12 / *dt, -Bp.a21 / *dt, Bp.a11 / *dt};
+            X1 = mul(minus_eye(b.D), Bi);  // Q1 = (D - I) B1'^-1
+            X3 = mul(Bi, minus_eye(Ap));   // Q3 = B1'^-1 (A1' - I)
+            sym3(H, out[0]);
+            sym3(X1, out[1]);
+            sym3(Bp, out[2]);
+            sym3(X3, out[3]);
+        }
+        return true;
+    }
+
+    double objective(const double h[3]) const {
+        double st[4][3], dt;
+        if (!stages(h, st, &dt)) return INFINITY;
+        double f = 1.0;
+        for (auto& x : st) f *= gamma_ratio(x);
+        return f;
+    }
+
+    // The feasibility equation c . h = rhs.
+    void equation(double c[3], double* rhs) const {
+        *rhs = b.B.a12 - b.B.a21;
+        if (type == 1) {
+            c[0] = -b.A.a21;
+            c[1] = b.A.a11 - b.A.a22;
+            c[2] = b.A.a12;
+        } else {
+            c[0] = b.D.a12;
+            c[1] = b.D.a22 - b.D.a11;
+            c[2] = -b.D.a21;
+        }
+    }
+};
+
+struct Cand {
+    double f;
+    double h[3];
+};
+
+bool better_tie(const Cand& x, const Cand& y) {
+    auto key = [](const Cand& c) {
+        std::array<double, 4> k{c.h[0] * c.h[0] + 2 * c.h[1] * c.h[1] + c.h[2] * c.h[2], c.h[0], c.h[1],
+                                c.h[2]};
+        for (auto& v : k) v = std::round(v * 1e12) / 1e12;
+        return k;
+    };
+    return key(x) < key(y);
+}
+
+struct GaugeOut {
+    bool feasible = false;
+    bool found = false;
+    double h[3] = {0, 0, 0};
+    double f = INFINITY;
+};
+
+// Nelder-Mead minimisation in dim (2 or 3) coordinates from s with an
+// axis-aligned initial simplex of size `size`; s is overwritten by the best
+// vertex, whose value is returned.
+template <class Fn>
+double nelder_mead(Fn& f, double* s, int dim, double size) {
+    const int n = dim;
+    double X[4][3], F[4];
+    for (int i = 0; i <= n; ++i) {
+        for (int k = 0; k < 3; ++k) X[i][k] = s[k];
+        if (i > 0) X[i][i - 1] += size;
+        F[i] = f(X[i]);
+    }
+    for (int it = 0; it < 20000; ++it) {
+        // Order vertices by value.
+        for (int i = 1; i <= n; ++i)
+            for (int j = i; j > 0 && F[j] < F[j - 1]; --j) {
+                std::swap(F[j], F[j - 1]);
+                for (int k = 0; k < 3; ++k) std::swap(X[j][k], X[j - 1][k]);
+            }
+        double xspan = 0;
+        for (int i = 1; i <= n; ++i)
+            for (int k = 0; k < n; ++k) xspan = std::max(xspan, std::fabs(X[i][k] - X[0][k]));
+        if (xspan <= 1e-12 * (1.0 + std::fabs(X[0][0]) + std::fabs(X[0][1])) ||
+            (std::isfinite(F[n]) && F[n] - F[0] <= 1e-14 * F[0] && xspan <= 1e-9))
+            break;
+        double c[3] = {0, 0, 0};
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) c[k] += X[i][k] / n;
+        auto along = [&](double t, double* out) {
+            for (int k = 0; k < 3; ++k) out[k] = k < n ? c[k] + t * (X[n][k] - c[k]) : X[0][k];
+        };
+        double xr[3], xe[3], xc[3];
+        along(-1.0, xr);
+        const double fr = f(xr);
+        if (fr < F[0]) {
+            along(-2.0, xe);
+            const double fe = f(xe);
+            if (fe < fr) {
+                std::memcpy(X[n], xe, sizeof xe);
+                F[n] = fe;
+            } else {
+                std::memcpy(X[n], xr, sizeof xr);
+                F[n] = fr;
+            }
+        } else if (fr < F[n - 1]) {
+            std::memcpy(X[n], xr, sizeof xr);
+            F[n] = fr;
+        } else {
+            const bool outside = fr < F[n];
+            along(outside ? -0.5 : 0.5, xc);
+            const double fc = f(xc);
+            if (fc < (outside ? fr : F[n])) {
+                std::memcpy(X[n], xc, sizeof xc);
+                F[n] = fc;
+            } else {
+                for (int i = 1; i <= n; ++i) {
+                    for (int k = 0; k < n; ++k) X[i][k] = X[0][k] + 0.5 * (X[i][k] - X[0][k]);
+                    F[i] = f(X[i]);
+                }
+            }
+        }
+    }
+    int b = 0;
+    for (int i = 1; i <= n; ++i)
+        if (F[i] < F[b]) b = i;
+    for (int k = 0; k < 3; ++k) s[k] = X[b][k];
+    return F[b];
+}
+
+// Exhaustive HA gauge search (eq. HA24).
+GaugeOut solve(const Gauge& g, double mmax) {
+    GaugeOut out;
+    double c[3], rhs;
+    g.equation(c, &rhs);
+    const double scale = std::max(1.0, mmax);
+    const double cn = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    double h0[3] = {0, 0, 0};
+    double U[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};  // columns span the feasible set
+    int dim;
+    if (cn <= 1e-12 * scale) {
+        if (std::fabs(rhs) > 1e-12 * scale) return out;  // 0 = rhs != 0: empty
+        dim = 3;
+    } else {
+        dim = 2;
+        const double u[3] = {c[0] / cn, c[1] / cn, c[2] / cn};
+        for (int i = 0; i < 3; ++i) h0[i] = u[i] * rhs / cn;
+        // Gram-Schmidt: start from the axis least aligned with c.
+        int ax = 0;
+        for (int i = 1; i < 3; ++i)
+            if (std::fabs(u[i]) < std::fabs(u[ax])) ax = i;
+        double e[3] = {0, 0, 0};
+        e[ax] = 1;
+        double d = u[ax];
+        double v1[3] = {e[0] - d * u[0], e[1] - d * u[1], e[2] - d * u[2]};
+        double n1 = std::sqrt(v1[0] * v1[0] + v1[1] * v1[1] + v1[2] * v1[2]);
+        for (auto& x : v1) x /= n1;
+        double v2[3] = {u[1] * v1[2] - u[2] * v1[1], u[2] * v1[0] - u[0] * v1[2], u[0] * v1[1] - u[1] * v1[0]};
+        for (int i = 0; i < 3; ++i) {
+            U[i][0] = v1[i];
+            U[i][1] = v2[i];
+            U[i][2] = 0;
+        }
+    }
+    out.feasible = true;
+    auto to_h = [&](const double* s, double* h) {
+        for (int i = 0; i < 3; ++i) {
+            h[i] = h0[i];
+            for (int k = 0; k < dim; ++k) h[i] += U[i][k] * s[k];
+        }
+    };
+    auto fs = [&](const double* s) {
+        double h[3];
+        to_h(s, h);
+        return g.objective(h);
+    };
+
+    const double R = 4.0 * (1.0 + mmax);
+    const int G = dim == 2 ? 513 : 81;
+    const double step = 2.0 * R / (G - 1);
+    // Grid evaluation.
+    std::vector<std::pair<double, std::array<int, 3>>> cells;
+    cells.reserve(dim == 2 ? G * G : G * G * G);
+    {
+        double s[3] = {0, 0, 0};
+        const int G3 = dim == 3 ? G : 1;
+        for (int i = 0; i < G; ++i)
+            for (int j = 0; j < G; ++j)
+                for (int k = 0; k < G3; ++k) {
+                    s[0] = -R + step * i;
+                    s[1] = -R + step * j;
+                    s[2] = -R + step * k;
+                    const double f = fs(s);
+                    if (std::isfinite(f)) cells.push_back({f, {i, j, k}});
+                }
+    }
+    if (cells.empty()) return out;
+    std::sort(cells.begin(), cells.end(),
+              [](const auto& x, const auto& y) { return x.first < y.first; });
+    std::vector<std::array<int, 3>> seeds;
+    for (const auto& cell : cells) {
+        bool far = true;
+        for (const auto& s : seeds) {
+            int dmax = 0;
+            for (int k = 0; k < dim; ++k) dmax = std::max(dmax, std::abs(cell.second[k] - s[k]));
+            if (dmax <= 3) far = false;
+        }
+        if (far) seeds.push_back(cell.second);
+        if (seeds.size() >= 16) break;
+    }
+
+    std::vector<Cand> cands;
+    for (const auto& sd : seeds) {
+        double s[3] = {-R + step * sd[0], -R + step * sd[1], -R + step * sd[2]};
+        if (dim == 2) s[2] = 0;
+        double f = nelder_mead(fs, s, dim, step);
+        // Restart from the result with a fresh simplex: Nelder-Mead can
+        // collapse early next to a kink.
+        for (int rs = 0; rs < 3; ++rs) f = nelder_mead(fs, s, dim, step * std::pow(0.1, rs + 1));
+        Cand cd;
+        cd.f = f;
+        to_h(s, cd.h);
+        cands.push_back(cd);
+
+        // Kink snapping: Newton on subsets of the near-zero stage entries.
+        double stg[4][3], dt;
+        if (!g.stages(cd.h, stg, &dt)) continue;
+        double emax = 0;
+        for (auto& x : stg)
+            for (double v : x) emax = std::max(emax, std::fabs(v));
+        std::vector<int> near;
+        for (int i = 0; i < 12; ++i)
+            if (std::fabs(stg[i / 3][i % 3]) < 1e-4 * (1 + emax)) near.push_back(i);
+        if (near.size() > 8) near.resize(8);
+        const int nn = (int)near.size();
+        auto entries = [&](const double* x, const int* idx, double* e) {
+            double h[3], st2[4][3], dd;
+            to_h(x, h);
+            if (!g.stages(h, st2, &dd)) return false;
+            for (int k = 0; k < dim; ++k) e[k] = st2[idx[k] / 3][idx[k] % 3];
+            return true;
+        };
+        std::vector<int> comb(dim);
+        std::function<void(int, int)> rec;
+        auto newton = [&](const int* idx) {
+            double x[3] = {s[0], s[1], s[2]};
+            double e[3];
+            if (!entries(x, idx, e)) return;
+            for (int it = 0; it < 60; ++it) {
+                double Jm[3][3];
+                for (int k = 0; k < dim; ++k) {
+                    const double hstep = 1e-7 * (1.0 + std::fabs(x[k]));
+                    double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+                    xp[k] += hstep;
+                    xm[k] -= hstep;
+                    double ep[3], em[3];
+                    if (!entries(xp, idx, ep) || !entries(xm, idx, em)) return;
+                    for (int r = 0; r < dim; ++r) Jm[r][k] = (ep[r] - em[r]) / (2 * hstep);
+                }
+                // Solve Jm dx = -e (dim 2 or 3) by Cramer's rule.
+                double dx[3] = {0, 0, 0};
+                if (dim == 2) {
+                    const double dj = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+                    if (std::fabs(dj) < 1e-300) return;
+                    dx[0] = (-e[0] * Jm[1][1] + e[1] * Jm[0][1]) / dj;
+                    dx[1] = (-e[1] * Jm[0][0] + e[0] * Jm[1][0]) / dj;
+                } else {
+                    auto d3 = [](double a[3][3]) {
+                        return a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                               a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                               a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+                    };
+                    const double dj = d3(Jm);
+                    if (std::fabs(dj) < 1e-300) return;
+                    for (int k = 0; k < 3; ++k) {
+                        double Mk[3][3];
+                        for (int r = 0; r < 3; ++r)
+                            for (int q = 0; q < 3; ++q) Mk[r][q] = (q == k) ? -e[r] : Jm[r][q];
+                        dx[k] = d3(Mk) / dj;
+                    }
+                }
+                for (int k = 0; k < dim; ++k) x[k] += dx[k];
+                if (!entries(x, idx, e)) return;
+                double em = 0;
+                for (int k = 0; k < dim; ++k) em = std::max(em, std::fabs(e[k]));
+                if (em <= 1e-13 * (1 + emax)) {
+                    Cand c2;
+                    to_h(x, c2.h);
+                    c2.f = g.objective(c2.h);
+                    if (std::isfinite(c2.f)) cands.push_back(c2);
+                    return;
+                }
+            }
+        };
+        rec = [&](int start, int depth) {
+            if (depth == dim) {
+                newton(comb.data());
+                return;
+            }
+            for (int i = start; i < nn; ++i) {
+                comb[depth] = near[i];
+                rec(i + 1, depth + 1);
+            }
+        };
+        rec(0, 0);
+    }
+    double fmin = INFINITY;
+    for (const auto& cd : cands) fmin = std::min(fmin, cd.f);
+    if (!std::isfinite(fmin)) return out;
+    const Cand* best = nullptr;
+    for (const auto& cd : cands) {
+        if (cd.f > fmin * (1.0 + 1e-9)) continue;
+        if (!best || better_tie(cd, *best)) best = &cd;
+    }
+    out.found = true;
+    out.f = best->f;
+    std::memcpy(out.h, best->h, sizeof out.h);
+    return out;
+}
+
+uint64_t turns_fixed(double kappa) {
+    // frac(kappa / 2 pi) as a 64-bit fixed-point fraction of a turn.
+    const double t = kappa / kTwoPi;
+    double f = t - std::floor(t);
+    if (!(f < 1.0)) f = 0.0;
+    return (uint64_t)std::ldexp(f, 64);
+}
+
+ChirpTurns make_turns(const double p[3], double du, double dv) {
+    ChirpTurns c;
+    c.c11 = turns_fixed(0.5 * p[0] * du * du);
+    c.c12 = turns_fixed(p[1] * du * dv);
+    c.c22 = turns_fixed(0.5 * p[2] * dv * dv);
+    c.nonzero = (p[0] != 0.0 || p[1] != 0.0 || p[2] != 0.0) ? 1 : 0;
+    return c;
+}
+
+bool pow2_size(int n) { return n >= 2 && n <= 4096 && (n & (n - 1)) == 0; }
+
+void fill_chains(PlanData* p) {
+    const nslct_stages& s = p->st;
+    double S[5][3] = {};
+    auto put = [&](int slot, const double* x, double sign) {
+        for (int k = 0; k < 3; ++k) S[slot][k] = sign * x[k];
+    };
+    // Generic form CM(S0) U CM_w(C1) U^H CM(S2) U CM_w(C3) U^H CM(S4), rightmost first.
+    if (s.type == 1) {  // CM(P1) CC(B') CM(P3) CC(H), CC(X) = F^-1 CM(-X) F
+        put(1, s.mats[3], -1.0);
+        put(2, s.mats[2], 1.0);
+        put(3, s.mats[1], -1.0);
+        put(4, s.mats[0], 1.0);
+    } else if (s.type == 2) {  // CC(H1) CM(Q1) CC(B1') CM(Q3)
+        put(0, s.mats[3], 1.0);
+        put(1, s.mats[2], -1.0);
+        put(2, s.mats[1], 1.0);
+        put(3, s.mats[0], -1.0);
+    } else {  // CM(C)
+        put(0, s.mats[0], 1.0);
+    }
+    for (int d = 0; d < 2; ++d) {
+        for (int k = 0; k < 5; ++k) {
+            // Adjoint: reversed order, negated matrices (eq. CCCMCCCM30).
+            const double* src = d == 0 ? S[k] : S[4 - k];
+            const double sg = d == 0 ? 1.0 : -1.0;
+            for (int q = 0; q < 3; ++q) p->dir[d].slot[k][q] = sg * src[q];
+            const bool freq = (k == 1 || k == 3);
+            p->dir[d].turns[k] = make_turns(p->dir[d].slot[k], freq ? s.dwx : s.dx, freq ? s.dwy : s.dy);
+        }
+    }
+}
+
+int check_common(int Nx, int Ny, double dx, double dy, const nslct_opts& o, std::string* err) {
+    if (!(dx > 0) || !(dy > 0) || !std::isfinite(dx) || !std::isfinite(dy)) {
+        *err = "sampling intervals must be finite and positive";
+        return NSLCT_E_ARG;
+    }
+    if (!pow2_size(Nx) || !pow2_size(Ny)) {
+        *err = "Nx and Ny must be powers of two in [2, 4096]";
+        return NSLCT_E_SIZE;
+    }
+    if (o.precision != NSLCT_C64 && o.precision != NSLCT_C128) {
+        *err = "unknown precision";
+        return NSLCT_E_ARG;
+    }
+    if (o.type_override < 0 || o.type_override > 2) {
+        *err = "type_override must be 0, 1 or 2";
+        return NSLCT_E_ARG;
+    }
+    return NSLCT_OK;
+}
+
+}  // namespace
+
+double gamma_ratio(const double x[3]) {
+    return (std::fabs(x[0]) + std::fabs(x[1]) + 1.0) * (std::fabs(x[1]) + std::fabs(x[2]) + 1.0);
+}
+
+int build_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, const nslct_opts& o,
+               PlanData* out, std::string* err) {
+    int rc = check_common(Nx, Ny, dx, dy, o, err);
+    if (rc) return rc;
+    for (int i = 0; i < 16; ++i)
+        if (!std::isfinite(abcd[i])) {
+            *err = "ABCD matrix has a non-finite entry";
+            return NSLCT_E_ARG;
+        }
+    const double res = symplectic_residual(abcd);
+    if (!(res <= o.symplectic_tol)) {
+        *err = "ABCD matrix is not symplectic: max|M J M^T - J| = " + std::to_string(res);
+        return NSLCT_E_NOT_SYMPLECTIC;
+    }
+    std::memset(out, 0, sizeof *out);
+    out->Nx = Nx;
+    out->Ny = Ny;
+    out->precision = o.precision;
+    nslct_stages& s = out->st;
+    s.dx = dx;
+    s.dy = dy;
+    s.dwx = kTwoPi / (Nx * dx);
+    s.dwy = kTwoPi / (Ny * dy);
+    s.symplectic_residual = res;
+    const Blocks b = split(abcd);
+    double bmax = std::max({std::fabs(b.B.a11), std::fabs(b.B.a12), std::fabs(b.B.a21), std::fabs(b.B.a22)});
+    double mmax = 0;
+    for (int i = 0; i < 16; ++i) mmax = std::max(mmax, std::fabs(abcd[i]));
+    if (bmax < 1e-12) {
+        const double ea = std::max({std::fabs(b.A.a11 - 1), std::fabs(b.A.a12), std::fabs(b.A.a21),
+                                    std::fabs(b.A.a22 - 1)});
+        const double ed = std::max({std::fabs(b.D.a11 - 1), std::fabs(b.D.a12), std::fabs(b.D.a21),
+                                    std::fabs(b.D.a22 - 1)});
+        if (ea < 1e-12 && ed < 1e-12) {
+            s.type = 0;
+            sym3(b.C, s.mats[0]);
+            s.gauge_objective = gamma_ratio(s.mats[0]);
+            fill_chains(out);
+            return NSLCT_OK;
+        }
+        *err = "B = 0 with A or D != I is an affine map, not decomposable into CMs and CCs";
+        return NSLCT_E_NO_DECOMPOSITION;
+    }
+    int type = o.type_override;
+    if (type == 0) type = (b.B.a11 + b.B.a22) < 0 ? 2 : 1;
+    Gauge g{b, type, 1e-6 * std::max(1.0, bmax * bmax)};
+    GaugeOut go = solve(g, mmax);
+    if (o.type_override == 0 && !go.feasible) {
+        g.type = type = 3 - type;
+        go = solve(g, mmax);
+    }
+    if (!go.found) {
+        *err = "no symmetric gauge H with invertible middle CC matrix (eqs. Bnonsym32, HA24)";
+        return NSLCT_E_NO_DECOMPOSITION;
+    }
+    s.type = type;
+    double dt;
+    g.stages(go.h, s.mats, &dt);
+    std::memcpy(s.h, go.h, sizeof s.h);
+    s.gauge_objective = go.f;
+    fill_chains(out);
+    return NSLCT_OK;
+}
+
+int build_plan_from_stages(const nslct_stages& st, int Nx, int Ny, const nslct_opts& o, PlanData* out,
+                           std::string* err) {
+    int rc = check_common(Nx, Ny, st.dx, st.dy, o, err);
+    if (rc) return rc;
+    if (st.type < 0 || st.type > 2) {
+        *err = "stage type must be 0, 1 or 2";
+        return NSLCT_E_ARG;
+    }
+    const int nm = st.type == 0 ? 1 : 4;
+    for (int i = 0; i < nm; ++i)
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(st.mats[i][k])) {
+                *err = "stage matrix has a non-finite entry";
+                return NSLCT_E_ARG;
+            }
+    std::memset(out, 0, sizeof *out);
+    out->Nx = Nx;
+    out->Ny = Ny;
+    out->precision = o.precision;
+    nslct_stages& s = out->st;
+    s.type = st.type;
+    for (int i = 0; i < nm; ++i)
+        for (int k = 0; k < 3; ++k) s.mats[i][k] = st.mats[i][k];
+    s.dx = st.dx;
+    s.dy = st.dy;
+    s.dwx = kTwoPi / (Nx * st.dx);
+    s.dwy = kTwoPi / (Ny * st.dy);
+    double f = 1.0;
+    for (int i = 0; i < nm; ++i) f *= gamma_ratio(s.mats[i]);
+    s.gauge_objective = f;
+    s.symplectic_residual = 0.0;
+    fill_chains(out);
+    return NSLCT_OK;
+}
+
+bool box_check(const PlanData& p, double frac) {
+    const nslct_stages& s = p.st;
+    double X = frac * p.Nx * s.dx / 2, Y = frac * p.Ny * s.dy / 2;
+    double Wx = frac * (0.5 * kTwoPi) / s.dx, Wy = frac * (0.5 * kTwoPi) / s.dy;
+    const double lX = p.Nx * s.dx / 2, lY = p.Ny * s.dy / 2, lWx = (0.5 * kTwoPi) / s.dx, lWy = (0.5 * kTwoPi) / s.dy;
+    // Forward chain slots in application order: CM(S0), CC via C1, CM(S2), CC via C3, CM(S4).
+    // A CC with chirp -X in the frequency domain shears positions by X (eq. HA20);
+    // a CM with matrix P shears frequencies by P z (eq. HA12).
+    const Chain5& c = p.dir[0];
+    auto ok = [&]() {
+        const double e = 1 + 1e-12;
+        return X <= lX * e && Y <= lY * e && Wx <= lWx * e && Wy <= lWy * e;
+    };
+    for (int k = 0; k < 5; ++k) {
+        const double* m = c.slot[k];
+        if (k == 1 || k == 3) {
+            const double nx = X + std::fabs(m[0]) * Wx + std::fabs(m[1]) * Wy;
+            const double ny = Y + std::fabs(m[1]) * Wx + std::fabs(m[2]) * Wy;
+            X = nx;
+            Y = ny;
+        } else {
+            if (m[0] == 0 && m[1] == 0 && m[2] == 0) continue;
+            const double nx = Wx + std::fabs(m[0]) * X + std::fabs(m[1]) * Y;
+            const double ny = Wy + std::fabs(m[1]) * X + std::fabs(m[2]) * Y;
+            Wx = nx;
+            Wy = ny;
+        }
+        if (!ok()) return false;
+    }
+    return true;
+}
+
+}  // namespace nslct

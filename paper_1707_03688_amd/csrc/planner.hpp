@@ -1,0 +1,47 @@
+// Host-side planning of the 2D HA-NsDLCT (FP64): validation of the ABCD
+// matrix, decomposition type, HA gauge search and the stage coefficients the
+// device passes consume.  No HIP calls: planning runs without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+
+#include "nslct.h"
+
+namespace nslct {
+
+// Quadratic phase phi(a, b) = c11*a^2 + c12*a*b + c22*b^2 in fixed-point
+// turns: 2^64 units = one turn, so integer wrap-around is the reduction
+// modulo 2*pi and a product with exact integer sample indices is exact.
+struct ChirpTurns {
+    uint64_t c11, c12, c22;
+    int nonzero;
+};
+
+// One of the chain's five "slots" in application order:
+//   CM(S0) -> F -> CM_w(C1) -> F^-1 -> CM(S2) -> F -> CM_w(C3) -> F^-1 -> CM(S4)
+// S slots act on the space grid (dx, dy), C slots on the frequency grid.
+struct Chain5 {
+    double slot[5][3];
+    ChirpTurns turns[5];
+};
+
+struct PlanData {
+    nslct_stages st;
+    int Nx, Ny;
+    int precision;
+    Chain5 dir[2];  // [0] forward, [1] inverse (adjoint)
+};
+
+// Symmetric 2x2 (x11, x12, x22) helpers exposed for tests of the planner.
+double gamma_ratio(const double x[3]);
+
+// Builds a plan; returns an NSLCT_* code and fills `err` on failure.
+int build_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, const nslct_opts& o,
+               PlanData* out, std::string* err);
+int build_plan_from_stages(const nslct_stages& st, int Nx, int Ny, const nslct_opts& o,
+                           PlanData* out, std::string* err);
+// Phase-space box check (eqs. HA12-HA20) with the input in fraction `frac`.
+bool box_check(const PlanData& p, double frac);
+
+}  // namespace nslct

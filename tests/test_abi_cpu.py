@@ -1,0 +1,145 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/nslct.h, validates its arguments, and
+its planner agrees with the oracle's gauge search."""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import gauge as ogauge, plan as oplan, symplectic
+from oracle_fixtures import paper_matrices
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def nl():
+    import paper_1707_03688_amd as _nl
+    return _nl
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "nslct.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nslct_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(nl):
+    names = _declared()
+    assert "nslct_forward" in names and "nslct_plan" in names
+    handle = ctypes.CDLL(nl._lib.LIB_PATH)
+    for n in names:
+        assert hasattr(handle, n), n
+
+
+def _cplan(nl, M, Nx=16, Ny=16, dx=1.0, dy=1.0, opts=None):
+    m = np.ascontiguousarray(np.asarray(M, dtype=np.float64).reshape(16))
+    h = ctypes.c_void_p()
+    o = nl.lib.opts() if opts is None else opts
+    rc = nl.lib.nslct_plan_ex(m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), Nx, Ny, dx, dy,
+                              ctypes.byref(o), ctypes.byref(h))
+    if rc == 0:
+        nl.lib.nslct_plan_destroy(h)
+    return rc
+
+
+def test_error_codes(nl):
+    M = synth.symplectic_candidates(0).__next__()
+    assert _cplan(nl, M) == 0
+    bad = M.copy()
+    bad[0, 0] += 1e-3
+    assert _cplan(nl, bad) == -2                       # NSLCT_E_NOT_SYMPLECTIC
+    assert _cplan(nl, M, Nx=12) == -4                  # NSLCT_E_SIZE
+    assert _cplan(nl, M, Nx=8192) == -4
+    assert _cplan(nl, M, dx=0.0) == -1                 # NSLCT_E_ARG
+    assert _cplan(nl, M, dy=float("nan")) == -1
+    affine = np.block([[2 * np.eye(2), np.zeros((2, 2))], [np.zeros((2, 2)), 0.5 * np.eye(2)]])
+    assert _cplan(nl, affine) == -3                    # B = 0, A != I
+    o = nl.lib.opts()
+    o.type_override = 7
+    assert _cplan(nl, M, opts=o) == -1
+    # Null pointers and misaligned buffers are rejected before any device work.
+    p = nl.Plan(M, 16, 16)
+    assert nl.lib.nslct_forward(p._h, None, None, None) == -1
+    assert nl.lib.nslct_forward(p._h, ctypes.c_void_p(1 << 20 | 8), ctypes.c_void_p(1 << 20), None) == -1
+    assert nl.lib.nslct_launch_pass(p._h, 0, 5, 1, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 20),
+                                    None) == -1
+    assert nl.lib.nslct_forward(None, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 20), None) == -1
+    assert b"null" in nl.lib.nslct_last_error()
+    assert nl.lib.nslct_strerror(-3) == b"no CM-CC-CM-CC decomposition"
+
+
+def test_pure_cm_plan(nl):
+    C = np.array([[0.3, -0.45], [-0.45, 1.1]])
+    M = np.block([[np.eye(2), np.zeros((2, 2))], [C, np.eye(2)]])
+    st = nl.Plan(M, 8, 8).stages()
+    assert st["type"] == 0
+    assert np.allclose(st["mats"][0], C, atol=0)
+
+
+def _cm4(P):
+    return np.block([[np.eye(2), np.zeros((2, 2))], [P, np.eye(2)]])
+
+
+def _cc4(B):
+    return np.block([[np.eye(2), B], [np.zeros((2, 2)), np.eye(2)]])
+
+
+def _draws():
+    out = []
+    for seed in range(4):
+        c = synth.symplectic_candidates(100 + seed)
+        out += [next(c) for _ in range(5)]
+    out += [symplectic.project(m) for m in paper_matrices().values()]
+    FT = np.block([[np.zeros((2, 2)), np.eye(2)], [-np.eye(2), np.zeros((2, 2))]])
+    out.append(FT)
+    return out
+
+
+def test_planner_agrees_with_oracle_gauge(nl):
+    """Same type; gauge objective equal to relative 1e-8 (two independent
+    searches of eq. HA24); planner stages multiply back to M (eq. Bnonsym08 /
+    CCCMCCCM12) and the planner's H is feasible and optimal for the oracle's
+    objective too."""
+    for M in _draws():
+        st = nl.Plan(M, 32, 32, 0.5, 0.5).stages()
+        po = oplan.plan(M, 32, 32, 0.5, 0.5)
+        assert st["type"] == po.typ
+        assert st["f"] == pytest.approx(po.f, rel=1e-8)
+        assert ogauge.objective(M, st["type"], st["h"]) == pytest.approx(po.f, rel=1e-8)
+        P = st["mats"]
+        prod = (_cm4(P[0]) @ _cc4(P[1]) @ _cm4(P[2]) @ _cc4(P[3]) if st["type"] == 1
+                else _cc4(P[0]) @ _cm4(P[1]) @ _cc4(P[2]) @ _cm4(P[3]))
+        assert np.max(np.abs(prod - M)) <= 1e-10 * max(1.0, np.max(np.abs(M)))
+
+
+def test_planner_type_override_and_pairing(nl):
+    """type_override forces a type; the inverse matrix gets the paired gauge
+    H1 = -H (eq. CCCMCCCM24)."""
+    M = symplectic.project(paper_matrices()["M2"])
+    p1 = nl.Plan(M, 16, 16).stages()
+    pi = nl.Plan(symplectic.inverse(M), 16, 16).stages()
+    assert (p1["type"], pi["type"]) == (1, 2)
+    assert np.max(np.abs(pi["h"] + p1["h"])) <= 1e-8
+    p2 = nl.Plan(M, 16, 16, type_override=2).stages()
+    assert p2["type"] == 2
+
+
+def test_plan_from_stages_roundtrip_and_box(nl):
+    mats = [np.array([[0.1, 0.02], [0.02, -0.05]]), np.array([[0.3, 0.1], [0.1, 0.2]]),
+            np.array([[0.0, 0.0], [0.0, 0.0]]), np.array([[-0.2, 0.0], [0.0, 0.1]])]
+    p = nl.Plan.from_stages(1, mats, 32, 64, 0.5, 0.25)
+    st = p.stages()
+    for a, b in zip(st["mats"], mats):
+        assert np.array_equal(a, b)
+    assert st["dwx"] == pytest.approx(2 * math.pi / (32 * 0.5))
+    assert p.box_check(0.5)
+    big = nl.Plan.from_stages(1, [m * 0 for m in mats[:1]] + [np.eye(2) * 50] + [m * 0 for m in mats[2:]],
+                              32, 32, 0.5, 0.5)
+    assert not big.box_check(0.5)
