@@ -38,7 +38,8 @@
  *   kernel shows up at the next synchronising HIP call.
  *
  * Sizes
- *   Nx, Ny are powers of two from 2 to 4096 (NSLCT_E_SIZE otherwise).
+ *   Nx, Ny are 2^k from 2 to 4096 or 3 * 2^k from 6 to 768 (NSLCT_E_SIZE
+ *   otherwise).
  */
 #ifndef NSLCT_H
 #define NSLCT_H
@@ -64,6 +65,7 @@ extern "C" {
 #define NSLCT_C128 1 /* complex128 storage and arithmetic */
 
 typedef struct nslct_plan_s* nslct_plan_t;
+typedef struct nslct_batch_s* nslct_batch_t;
 
 /* Planning options; initialise with nslct_opts_default. */
 typedef struct {
@@ -132,6 +134,36 @@ int nslct_inverse_many(nslct_plan_t plan, int count, const void* in, void* out, 
  * equals nslct_forward_many / nslct_inverse_many.  For profiling. */
 int nslct_launch_pass(nslct_plan_t plan, int direction, int pass, int count,
                       const void* in, void* out, void* stream);
+
+/* Ragged batch: `count` plans (each with its own matrix and size) over one
+ * packed buffer in which image i occupies samples [off_i, off_i + Nx_i Ny_i),
+ * off_0 = 0, images back to back in plan order.  All plans must share one
+ * precision; sides must be 64, 128, 192, 256, 384, 512, 768 or 1024.  The
+ * batch copies the plans (they may be destroyed afterwards), uploads a
+ * per-image descriptor table and an XCD-balanced work list to the current
+ * device, and autotunes the grid of its persistent pass kernels on scratch
+ * images (device work and allocation happen here, once).  Not reentrant:
+ * calls on one batch from several threads are serialised internally. */
+int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out);
+
+/* Packed buffer length in samples, the autotuned persistent grid (workgroups
+ * per CU; 0 = one workgroup per work item) and the forward time measured
+ * while tuning, in microseconds (any pointer may be NULL). */
+int nslct_batch_info(nslct_batch_t batch, size_t* total_samples, int* mult, double* tuned_us);
+
+/* Forward / inverse of every image of the batch: the five passes, each one
+ * persistent launch per line length over all images of that length (the
+ * launches of one pass run concurrently), captured once per (in, out) pair
+ * into a HIP graph that is then replayed on `stream`.  in == out allowed. */
+int nslct_forward_batched(nslct_batch_t batch, const void* in, void* out, void* stream);
+int nslct_inverse_batched(nslct_batch_t batch, const void* in, void* out, void* stream);
+
+/* Same work with an explicit execution mode: 0 graph replay (as above),
+ * 1 the five batched launches without a graph, 2 one chain of launches per
+ * image (the reference loop).  direction 0 forward, 1 inverse. */
+int nslct_batch_run(nslct_batch_t batch, int direction, int mode, const void* in, void* out, void* stream);
+
+void nslct_batch_destroy(nslct_batch_t batch);
 
 /* Plain device-to-device copy kernel of `bytes` bytes (multiple of 16): the
  * bandwidth reference the transform is measured against. */

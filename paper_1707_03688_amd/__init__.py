@@ -14,7 +14,7 @@ import numpy as np
 
 from ._lib import (NSLCT_C64, NSLCT_C128, NslctError, Stages, lib, check)  # noqa: F401
 
-__all__ = ["Plan", "NslctError", "lib", "device_copy", "NSLCT_C64", "NSLCT_C128"]
+__all__ = ["Plan", "Batch", "NslctError", "lib", "device_copy", "NSLCT_C64", "NSLCT_C128"]
 
 _PRECISION = {"c64": NSLCT_C64, "c128": NSLCT_C128}
 
@@ -148,3 +148,64 @@ def device_copy(src, dst, stream=None):
     check(lib.nslct_device_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                 ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream_ptr(stream))))
     return dst
+
+
+class Batch:
+    """A ragged batch of plans over one packed buffer (``nslct_batch_create``).
+
+    Image i occupies samples [offsets[i], offsets[i] + Nx_i * Ny_i) of a flat
+    complex tensor of ``total`` samples.  ``forward`` / ``inverse`` replay a
+    captured HIP graph of the batched passes; ``run(mode=2)`` is the per-image
+    reference loop.
+    """
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        check(lib.nslct_batch_create(arr, len(self.plans), ctypes.byref(h)))
+        self._h = h
+        total = ctypes.c_size_t()
+        mult = ctypes.c_int()
+        tuned = ctypes.c_double()
+        check(lib.nslct_batch_info(h, ctypes.byref(total), ctypes.byref(mult), ctypes.byref(tuned)))
+        self.total = int(total.value)
+        self.mult = int(mult.value)
+        self.tuned_us = float(tuned.value)
+        self.precision = self.plans[0].precision
+        self.offsets = []
+        off = 0
+        for p in self.plans:
+            self.offsets.append(off)
+            off += p.Nx * p.Ny
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            lib.nslct_batch_destroy(h)
+            self._h = None
+
+    def _check(self, x):
+        torch = _torch()
+        want = torch.complex64 if self.precision == "c64" else torch.complex128
+        if x.dtype != want or not x.is_cuda or not x.is_contiguous() or x.numel() != self.total:
+            raise ValueError(f"expected a contiguous {want} GPU tensor of {self.total} samples")
+
+    def run(self, x, out=None, direction: int = 0, mode: int = 0, stream=None):
+        self._check(x)
+        if out is None:
+            out = _torch().empty_like(x)
+        self._check(out)
+        check(lib.nslct_batch_run(self._h, int(direction), int(mode), ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream_ptr(stream))))
+        return out
+
+    def forward(self, x, out=None, stream=None):
+        return self.run(x, out, 0, 0, stream)
+
+    def inverse(self, x, out=None, stream=None):
+        return self.run(x, out, 1, 0, stream)
+
+    def views(self, flat):
+        """Per-image [Nx, Ny] views of a packed tensor."""
+        return [flat[o:o + p.Nx * p.Ny].view(p.Nx, p.Ny) for o, p in zip(self.offsets, self.plans)]

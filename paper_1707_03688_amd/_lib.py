@@ -42,7 +42,7 @@ def _load():
     except ImportError:  # pragma: no cover - torch is part of the image
         pass
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1707_03688_amd.build")
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1707_03688_amd/build.py")
     return ctypes.CDLL(LIB_PATH)
 
 
@@ -65,6 +65,12 @@ SIGNATURES = {
     "nslct_inverse_many": (I, [P, I, P, P, P]),
     "nslct_launch_pass": (I, [P, I, I, I, P, P, P]),
     "nslct_device_copy": (I, [P, P, ctypes.c_size_t, P]),
+    "nslct_batch_create": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P)]),
+    "nslct_batch_info": (I, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(I), ctypes.POINTER(D)]),
+    "nslct_forward_batched": (I, [P, P, P, P]),
+    "nslct_inverse_batched": (I, [P, P, P, P]),
+    "nslct_batch_run": (I, [P, I, I, P, P, P]),
+    "nslct_batch_destroy": (None, [P]),
     "nslct_last_error": (ctypes.c_char_p, []),
     "nslct_strerror": (ctypes.c_char_p, [I]),
     "nslct_version": (ctypes.c_char_p, []),

@@ -1,6 +1,6 @@
 """Builds libnslct.so (HIP kernels for gfx950 + host planner + C ABI) in-tree.
 
-    python -m paper_1707_03688_amd.build        # or build() from Python
+    python paper_1707_03688_amd/build.py        # or __graft_entry__.build()
 
 Every call recompiles.  Packed FP32 instructions are disabled for all device
 code (``-packed-fp32-ops``).

@@ -1,7 +1,7 @@
 // Device-side building blocks of the fused NsDLCT passes (gfx950).
 //
 //  * cplx<T>            interleaved complex value in registers
-//  * dft_reg<R, S>      R-point DFT (R = 2..64) fully in registers, exponent
+//  * dft_reg<R, S>      R-point DFT (R = 2^a 3^b up to 64) in registers, exponent
 //                       sign S (-1 forward, +1 inverse), compile-time twiddles
 //  * LineFFT<T, N, ...> an N-point line DFT spread over TPL threads of a
 //                       workgroup: mixed-radix Stockham stages, each thread
@@ -50,35 +50,68 @@ __device__ __forceinline__ cplx<T> mul_si(cplx<T> a) {
         return {a.im, -a.re};
 }
 
-// cos(2 pi k / 64), k = 0..63 (sin(2 pi k/64) = entry (k + 48) mod 64).
-constexpr double kCos64[64] = {
-    1.0, 0.9951847266721969, 0.9807852804032304, 0.9569403357322088,
-    0.9238795325112867, 0.881921264348355, 0.8314696123025452, 0.773010453362737,
-    0.7071067811865476, 0.6343932841636455, 0.5555702330196023, 0.4713967368259978,
-    0.38268343236508984, 0.29028467725446233, 0.19509032201612833, 0.09801714032956077,
-    0.0, -0.09801714032956065, -0.1950903220161282, -0.29028467725446216,
-    -0.3826834323650897, -0.4713967368259977, -0.555570233019602, -0.6343932841636454,
-    -0.7071067811865475, -0.773010453362737, -0.8314696123025453, -0.8819212643483549,
-    -0.9238795325112867, -0.9569403357322088, -0.9807852804032304, -0.9951847266721968,
-    -1.0, -0.9951847266721969, -0.9807852804032304, -0.9569403357322089,
-    -0.9238795325112868, -0.881921264348355, -0.8314696123025455, -0.7730104533627371,
-    -0.7071067811865477, -0.6343932841636459, -0.5555702330196022, -0.47139673682599786,
-    -0.38268343236509034, -0.29028467725446244, -0.19509032201612866, -0.09801714032956045,
-    0.0, 0.09801714032956009, 0.1950903220161283, 0.29028467725446205,
-    0.38268343236509, 0.4713967368259976, 0.5555702330196018, 0.6343932841636456,
-    0.7071067811865474, 0.7730104533627367, 0.8314696123025452, 0.8819212643483548,
-    0.9238795325112865, 0.9569403357322088, 0.9807852804032303, 0.9951847266721969};
+// cos(2 pi k / 192), k = 0..191 (sin(2 pi k/192) = entry (k + 144) mod 192).
+// 192 = 3 * 64 covers every in-register twiddle of radices built from 2, 3, 4.
+constexpr double kCos192[192] = {
+    1.0, 0.9994645874763657, 0.9978589232386035, 0.9951847266721969,
+    0.9914448613738104, 0.986643332084879, 0.9807852804032304, 0.9738769792773336,
+    0.9659258262890683, 0.9569403357322088, 0.9469301294951057, 0.9359059267573258,
+    0.9238795325112867, 0.9108638249211758, 0.8968727415326884, 0.881921264348355,
+    0.8660254037844387, 0.8492021815265789, 0.8314696123025452, 0.8128466845916152,
+    0.7933533402912352, 0.773010453362737, 0.7518398074789774, 0.7298640726978357,
+    0.7071067811865476, 0.6835923020228712, 0.6593458151000688, 0.6343932841636455,
+    0.6087614290087207, 0.5824776968678022, 0.5555702330196024, 0.5280678506503681,
+    0.5000000000000001, 0.4713967368259976, 0.44228869021900125, 0.4127070298043947,
+    0.38268343236508984, 0.3522500479212336, 0.3214394653031617, 0.2902846772544625,
+    0.25881904510252074, 0.22707626303437345, 0.19509032201612833, 0.16289547339458882,
+    0.1305261922200517, 0.09801714032956055, 0.06540312923014327, 0.032719082821776165,
+    0.0, -0.03271908282177604, -0.06540312923014314, -0.09801714032956042,
+    -0.1305261922200516, -0.1628954733945887, -0.1950903220161282, -0.2270762630343733,
+    -0.25881904510252063, -0.29028467725446216, -0.3214394653031616, -0.3522500479212335,
+    -0.3826834323650895, -0.4127070298043946, -0.44228869021900113, -0.4713967368259977,
+    -0.4999999999999998, -0.528067850650368, -0.5555702330196023, -0.582477696867802,
+    -0.6087614290087207, -0.6343932841636454, -0.6593458151000688, -0.6835923020228714,
+    -0.7071067811865475, -0.7298640726978354, -0.7518398074789773, -0.773010453362737,
+    -0.793353340291235, -0.8128466845916151, -0.831469612302545, -0.8492021815265788,
+    -0.8660254037844387, -0.8819212643483549, -0.8968727415326881, -0.9108638249211759,
+    -0.9238795325112867, -0.9359059267573258, -0.9469301294951056, -0.9569403357322087,
+    -0.9659258262890682, -0.9738769792773336, -0.9807852804032304, -0.986643332084879,
+    -0.9914448613738104, -0.9951847266721968, -0.9978589232386035, -0.9994645874763657,
+    -1.0, -0.9994645874763657, -0.9978589232386035, -0.9951847266721969,
+    -0.9914448613738104, -0.986643332084879, -0.9807852804032305, -0.9738769792773336,
+    -0.9659258262890683, -0.9569403357322088, -0.9469301294951057, -0.9359059267573259,
+    -0.9238795325112868, -0.910863824921176, -0.8968727415326883, -0.881921264348355,
+    -0.8660254037844388, -0.8492021815265789, -0.8314696123025455, -0.812846684591615,
+    -0.7933533402912352, -0.7730104533627371, -0.7518398074789775, -0.7298640726978359,
+    -0.7071067811865479, -0.6835923020228712, -0.6593458151000691, -0.6343932841636459,
+    -0.6087614290087209, -0.5824776968678023, -0.5555702330196022, -0.5280678506503678,
+    -0.5000000000000004, -0.47139673682599786, -0.44228869021900136, -0.41270702980439467,
+    -0.3826834323650895, -0.35225004792123393, -0.3214394653031618, -0.29028467725446244,
+    -0.25881904510252063, -0.22707626303437292, -0.19509032201612866, -0.16289547339458896,
+    -0.13052619222005163, -0.09801714032956134, -0.06540312923014273, -0.03271908282177651,
+    0.0, 0.032719082821776144, 0.06540312923014237, 0.09801714032956096,
+    0.13052619222005127, 0.1628954733945886, 0.1950903220161283, 0.22707626303437256,
+    0.2588190451025203, 0.29028467725446205, 0.3214394653031615, 0.35225004792123354,
+    0.38268343236508917, 0.41270702980439433, 0.442288690219001, 0.4713967368259976,
+    0.5000000000000001, 0.5280678506503674, 0.5555702330196018, 0.5824776968678019,
+    0.6087614290087199, 0.6343932841636449, 0.6593458151000691, 0.6835923020228717,
+    0.7071067811865474, 0.7298640726978356, 0.7518398074789775, 0.7730104533627367,
+    0.7933533402912349, 0.8128466845916151, 0.8314696123025448, 0.8492021815265786,
+    0.8660254037844384, 0.8819212643483553, 0.8968727415326883, 0.9108638249211758,
+    0.9238795325112868, 0.9359059267573255, 0.9469301294951056, 0.9569403357322088,
+    0.9659258262890681, 0.9738769792773335, 0.9807852804032303, 0.9866433320848791,
+    0.9914448613738104, 0.9951847266721969, 0.9978589232386035, 0.9994645874763657};
 
-// v * exp(S 2 pi i e / L) for compile-time L | 64 and e (after unrolling).
+// v * exp(S 2 pi i e / L) for compile-time L | 192 and e (after unrolling).
 template <int S, typename T>
 __device__ __forceinline__ cplx<T> twiddle_ct(cplx<T> v, int L, int e) {
-    const int k = ((e % L) + L) % L * (64 / L);
+    const int k = ((e % L) + L) % L * (192 / L);
     if (k == 0) return v;
-    if (k == 16) return mul_si<S>(v);
-    if (k == 32) return {-v.re, -v.im};
-    if (k == 48) return mul_si<-S>(v);
-    const T c = (T)kCos64[k];
-    const T s = (T)(S * kCos64[(k + 48) & 63]);
+    if (k == 48) return mul_si<S>(v);
+    if (k == 96) return {-v.re, -v.im};
+    if (k == 144) return mul_si<-S>(v);
+    const T c = (T)kCos192[k];
+    const T s = (T)(S * kCos192[(k + 144) % 192]);
     return cmul(v, cplx<T>{c, s});
 }
 
@@ -99,15 +132,30 @@ __device__ __forceinline__ void dft4(cplx<T>* v) {
     v[3] = csub(d02, d13);
 }
 
+// y1 = a + w b + w^2 c with w = exp(S 2 pi i / 3) = -1/2 + S i sqrt(3)/2.
+template <int S, typename T>
+__device__ __forceinline__ void dft3(cplx<T>* v) {
+    const T h = (T)0.86602540378443864676;  // sqrt(3)/2
+    const cplx<T> s = cadd(v[1], v[2]);
+    const cplx<T> d = csub(v[1], v[2]);
+    const cplx<T> m = {v[0].re - (T)0.5 * s.re, v[0].im - (T)0.5 * s.im};
+    const cplx<T> r = mul_si<S>(cplx<T>{h * d.re, h * d.im});
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+}
+
 template <int R, int S, typename T>
 __device__ __forceinline__ void dft_base(cplx<T>* v) {
     if constexpr (R == 2)
         dft2<S>(v);
+    else if constexpr (R == 3)
+        dft3<S>(v);
     else if constexpr (R == 4)
         dft4<S>(v);
 }
 
-// One in-register Stockham stage of an R-point DFT with radix r (r = 2 or 4).
+// One in-register Stockham stage of an R-point DFT with radix r (2, 3 or 4).
 template <int R, int r, int Ns, int S, typename T>
 __device__ __forceinline__ void reg_stage(cplx<T>* x) {
     cplx<T> y[R];
@@ -131,7 +179,7 @@ template <int R, int Ns, int S, typename T>
 __device__ __forceinline__ void reg_stages(cplx<T>* v) {
     if constexpr (Ns < R) {
         constexpr int rem = R / Ns;
-        constexpr int r = (rem % 4 == 0) ? 4 : 2;
+        constexpr int r = (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : 3;
         reg_stage<R, r, Ns, S>(v);
         reg_stages<R, Ns * r, S>(v);
     }
@@ -140,7 +188,7 @@ __device__ __forceinline__ void reg_stages(cplx<T>* v) {
 // R-point DFT in registers, natural order in and out.
 template <int R, int S, typename T>
 __device__ __forceinline__ void dft_reg(cplx<T>* v) {
-    if constexpr (R == 2 || R == 4)
+    if constexpr (R == 2 || R == 3 || R == 4)
         dft_base<R, S>(v);
     else
         reg_stages<R, 1, S>(v);
@@ -151,10 +199,6 @@ struct RList {};
 
 template <int A, int... Rest>
 struct First {
-    static constexpr int value = A;
-};
-template <int A>
-struct Last1 {
     static constexpr int value = A;
 };
 template <int... R>
@@ -233,6 +277,47 @@ struct LinePlan<4096> {
     using L = RList<16, 16, 16>;
 };
 
+template <>
+struct LinePlan<6> {
+    static constexpr int TPL = 1;
+    using L = RList<6>;
+};
+template <>
+struct LinePlan<12> {
+    static constexpr int TPL = 1;
+    using L = RList<12>;
+};
+template <>
+struct LinePlan<24> {
+    static constexpr int TPL = 1;
+    using L = RList<24>;
+};
+template <>
+struct LinePlan<48> {
+    static constexpr int TPL = 4;
+    using L = RList<4, 3, 4>;
+};
+template <>
+struct LinePlan<96> {
+    static constexpr int TPL = 8;
+    using L = RList<4, 6, 4>;
+};
+template <>
+struct LinePlan<192> {
+    static constexpr int TPL = 8;
+    using L = RList<8, 3, 8>;
+};
+template <>
+struct LinePlan<384> {
+    static constexpr int TPL = 16;
+    using L = RList<8, 6, 8>;
+};
+template <>
+struct LinePlan<768> {
+    static constexpr int TPL = 32;
+    using L = RList<8, 12, 8>;
+};
+
 // LDS index of line position p (one padding element every 16).
 __device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
 template <int N>
@@ -240,29 +325,94 @@ constexpr int lds_line_elems() {
     return N + (N >> 4) + 1;
 }
 
-// Twiddle tables W_NT^k = exp(-2 pi i k / NT), filled once per device.
-constexpr int kTwiddleN = 4096;
+// Twiddle tables W_NT^k = exp(-2 pi i k / NT), filled once per device;
+// NT = 3 * 4096 serves every supported N (N divides NT).
+constexpr int kTwiddleN = 12288;
+
+// Orders this wavefront's LDS writes before its later LDS reads (a line
+// that lives inside one wavefront needs no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T, int N, int TPL>
 struct LineFFT {
     static constexpr int E = N / TPL;
+    // A line owned by at most one wavefront synchronises at wavefront scope.
+    static constexpr bool kWave = TPL <= 64;
+
+    __device__ __forceinline__ static void sync() {
+        if constexpr (kWave)
+            wave_lds_sync();
+        else
+            __syncthreads();
+    }
+
+    // Stages whose twiddle exponent k = j mod Ns is the same for all of a
+    // thread's butterflies (TPL a multiple of Ns) keep their R-1 twiddles in
+    // registers, loaded once per kernel; the others read the table.
+    template <int Ns, int R>
+    static constexpr bool preloaded() {
+        return Ns > 1 && TPL % Ns == 0;
+    }
+    template <int Ns, int R, int... Rest>
+    static constexpr int tw_count() {
+        constexpr int here = preloaded<Ns, R>() ? R - 1 : 0;
+        if constexpr (sizeof...(Rest) > 0)
+            return here + tw_count<Ns * R, Rest...>();
+        else
+            return here;
+    }
+    template <int... R>
+    static constexpr int tw_total(RList<R...>) {
+        return tw_count<1, R...>();
+    }
+    static constexpr int TW = tw_total(typename LinePlan<N>::L{}) > 0 ? tw_total(typename LinePlan<N>::L{}) : 1;
+
+    template <int Ns, int R, int... Rest>
+    __device__ __forceinline__ static void preload_from(cplx<T>* w, int off, int t, const cplx<T>* __restrict__ tab) {
+        if constexpr (preloaded<Ns, R>()) {
+            const int k = t % Ns;
+            constexpr int step = kTwiddleN / (Ns * R);
+#pragma unroll
+            for (int q = 1; q < R; ++q) w[off + q - 1] = tab[((q * k) % (Ns * R)) * step];
+        }
+        if constexpr (sizeof...(Rest) > 0)
+            preload_from<Ns * R, Rest...>(w, off + (preloaded<Ns, R>() ? R - 1 : 0), t, tab);
+    }
+    template <int... R>
+    __device__ __forceinline__ static void preload_list(RList<R...>, cplx<T>* w, int t,
+                                                        const cplx<T>* __restrict__ tab) {
+        preload_from<1, R...>(w, 0, t, tab);
+    }
+    // Loads this thread's register twiddles (forward sign) for all stages.
+    __device__ __forceinline__ static void preload(cplx<T>* w, int t, const cplx<T>* __restrict__ tab) {
+        preload_list(typename LinePlan<N>::L{}, w, t, tab);
+    }
 
     // One Stockham stage (twiddles + radix-R butterflies) on the registers.
-    template <int S, int Ns, int R>
-    __device__ __forceinline__ static void stage(cplx<T>* v, int t, const cplx<T>* __restrict__ tw) {
+    template <int S, int Ns, int R, int OFF>
+    __device__ __forceinline__ static void stage(cplx<T>* v, int t, const cplx<T>* w,
+                                                 const cplx<T>* __restrict__ tab) {
         static_assert(E % R == 0, "radix must divide the per-thread sample count");
 #pragma unroll
         for (int i = 0; i < E / R; ++i) {
             if constexpr (Ns > 1) {
-                const int j = t + TPL * i;
-                const int k = j % Ns;
-                constexpr int step = kTwiddleN / (Ns * R);
 #pragma unroll
                 for (int q = 1; q < R; ++q) {
-                    const int e = (q * k) % (Ns * R);
-                    cplx<T> w = tw[e * step];
-                    if constexpr (S > 0) w.im = -w.im;
-                    v[i * R + q] = cmul(v[i * R + q], w);
+                    cplx<T> tw;
+                    if constexpr (preloaded<Ns, R>()) {
+                        tw = w[OFF + q - 1];
+                    } else {
+                        const int j = t + TPL * i;
+                        const int k = j % Ns;
+                        constexpr int step = kTwiddleN / (Ns * R);
+                        tw = tab[((q * k) % (Ns * R)) * step];
+                    }
+                    if constexpr (S > 0) tw.im = -tw.im;
+                    v[i * R + q] = cmul(v[i * R + q], tw);
                 }
             }
             dft_reg<R, S>(&v[i * R]);
@@ -280,39 +430,39 @@ struct LineFFT {
 #pragma unroll
             for (int q = 0; q < R; ++q) lds[lds_pad(base + q * Ns)] = v[i * R + q];
         }
-        __syncthreads();
+        sync();
 #pragma unroll
         for (int i = 0; i < E / Rn; ++i) {
             const int j = t + TPL * i;
 #pragma unroll
             for (int q = 0; q < Rn; ++q) v[i * Rn + q] = lds[lds_pad(j + q * (N / Rn))];
         }
-        __syncthreads();
+        sync();
     }
 
-    template <int S, int Ns, int R, int... Rest>
-    __device__ __forceinline__ static void run_stages(cplx<T>* v, cplx<T>* lds, int t,
-                                                      const cplx<T>* __restrict__ tw) {
-        stage<S, Ns, R>(v, t, tw);
+    template <int S, int Ns, int OFF, int R, int... Rest>
+    __device__ __forceinline__ static void run_stages(cplx<T>* v, cplx<T>* lds, int t, const cplx<T>* w,
+                                                      const cplx<T>* __restrict__ tab) {
+        stage<S, Ns, R, OFF>(v, t, w, tab);
         if constexpr (sizeof...(Rest) > 0) {
             constexpr int Rn = First<Rest...>::value;
             exchange<Ns, R, Rn>(v, lds, t);
-            run_stages<S, Ns * R, Rest...>(v, lds, t, tw);
+            run_stages<S, Ns * R, OFF + (preloaded<Ns, R>() ? R - 1 : 0), Rest...>(v, lds, t, w, tab);
         }
     }
 
     template <int S, int... R>
-    __device__ __forceinline__ static void run(RList<R...>, cplx<T>* v, cplx<T>* lds, int t,
-                                               const cplx<T>* __restrict__ tw) {
-        run_stages<S, 1, R...>(v, lds, t, tw);
+    __device__ __forceinline__ static void run(RList<R...>, cplx<T>* v, cplx<T>* lds, int t, const cplx<T>* w,
+                                               const cplx<T>* __restrict__ tab) {
+        run_stages<S, 1, 0, R...>(v, lds, t, w, tab);
     }
 
     // Full line DFT with exponent sign S: registers hold positions
     // t + TPL*i + q*(N/R0) before and after (R0 = first = last radix).
     template <int S>
-    __device__ __forceinline__ static void dft(cplx<T>* v, cplx<T>* lds, int t,
-                                               const cplx<T>* __restrict__ tw) {
-        run<S>(typename LinePlan<N>::L{}, v, lds, t, tw);
+    __device__ __forceinline__ static void dft(cplx<T>* v, cplx<T>* lds, int t, const cplx<T>* w,
+                                               const cplx<T>* __restrict__ tab) {
+        run<S>(typename LinePlan<N>::L{}, v, lds, t, w, tab);
     }
 
     template <int... R>
@@ -326,6 +476,7 @@ struct LineFFT {
     static constexpr int R0 = first_radix(typename LinePlan<N>::L{});
     static_assert(R0 == last_radix(typename LinePlan<N>::L{}), "first and last radix must match");
     static_assert(E % R0 == 0, "bad line plan");
+    static_assert(R0 % 2 == 0, "the chirp index split assumes an even first radix");
 };
 
 }  // namespace nslct

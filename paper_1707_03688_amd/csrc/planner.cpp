@@ -441,7 +441,15 @@ ChirpTurns make_turns(const double p[3], double du, double dv) {
     return c;
 }
 
-bool pow2_size(int n) { return n >= 2 && n <= 4096 && (n & (n - 1)) == 0; }
+// Supported line lengths: 2^k (2..4096) and 3 * 2^k (6..768).
+bool supported_size(int n) {
+    if (n >= 2 && n <= 4096 && (n & (n - 1)) == 0) return true;
+    if (n % 3 == 0 && n >= 6 && n <= 768) {
+        const int m = n / 3;
+        return (m & (m - 1)) == 0;
+    }
+    return false;
+}
 
 void fill_chains(PlanData* p) {
     const nslct_stages& s = p->st;
@@ -480,8 +488,8 @@ int check_common(int Nx, int Ny, double dx, double dy, const nslct_opts& o, std:
         *err = "sampling intervals must be finite and positive";
         return NSLCT_E_ARG;
     }
-    if (!pow2_size(Nx) || !pow2_size(Ny)) {
-        *err = "Nx and Ny must be powers of two in [2, 4096]";
+    if (!supported_size(Nx) || !supported_size(Ny)) {
+        *err = "Nx and Ny must be 2^k in [2, 4096] or 3 * 2^k in [6, 768]";
         return NSLCT_E_SIZE;
     }
     if (o.precision != NSLCT_C64 && o.precision != NSLCT_C128) {

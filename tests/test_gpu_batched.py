@@ -1,0 +1,98 @@
+"""GPU tests of the ragged batched path (nslct_batch_*): every image of a
+batch with its own matrix and size, against the per-image launch loop
+(bitwise, same kernels) and against the FP64 oracle (element by element);
+graph replays interleaved with other work."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import chain, plan as oplan
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def nl(torch):
+    import paper_1707_03688_amd as _nl
+    return _nl
+
+
+def _batch(nl, sizes, seed, precision="c64", rect=False):
+    cands = synth.symplectic_candidates(seed)
+    plans, oplans = [], []
+    for i, s in enumerate(sizes):
+        M = next(cands)
+        Nx, Ny = (s, sizes[(i + 1) % len(sizes)]) if rect else (s, s)
+        d = (2 * np.pi / max(Nx, Ny)) ** 0.5
+        po = oplan.plan(M, Nx, Ny, d, d)
+        plans.append(nl.Plan.from_stages(po.typ, po.mats, Nx, Ny, d, d, precision))
+        oplans.append(po)
+    return nl.Batch(plans), oplans
+
+
+@pytest.mark.parametrize("rect", [False, True])
+def test_batched_matches_loop_bitwise_and_oracle(torch, nl, rect):
+    sizes = [64, 384, 128, 768, 256, 192, 512, 64, 128, 384]
+    b, oplans = _batch(nl, sizes, seed=31, rect=rect)
+    g = synth.complex_normal((b.total,), seed=2)
+    x = torch.from_numpy(g).to(torch.complex64).cuda()
+    out_graph = b.forward(x)
+    out_plain = b.run(x, mode=1)
+    out_loop = b.run(x, mode=2)
+    torch.cuda.synchronize()
+    assert torch.equal(out_graph, out_loop)
+    assert torch.equal(out_plain, out_loop)
+    got = out_graph.cpu().numpy()
+    for o, p, po in zip(b.offsets, b.plans, oplans):
+        gi = g[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny)
+        if p.Nx * p.Ny <= 384 * 384:
+            ref = chain.forward(po, gi)
+            assert chain.rel_l2(got[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny), ref) <= 1e-5
+    back = b.inverse(out_graph).cpu().numpy()
+    assert chain.rel_l2(back, g) <= 1e-5
+
+
+def test_graph_replays_are_stable(torch, nl):
+    """Repeated graph replays with unrelated eager work between them all equal
+    the eager (non-graph) result; in-place replays too."""
+    b, _ = _batch(nl, [256, 128, 384, 64], seed=32)
+    x = torch.from_numpy(synth.complex_normal((b.total,), seed=3)).to(torch.complex64).cuda()
+    ref = b.run(x, mode=1)
+    out = torch.empty_like(x)
+    for k in range(4):
+        b.forward(x, out=out)
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {k}"
+        del junk
+    y = x.clone()
+    b.forward(y, out=y)
+    assert torch.equal(y, ref)
+
+
+def test_batched_c128(torch, nl):
+    b, oplans = _batch(nl, [64, 96 * 2, 128], seed=33, precision="c128")
+    g = synth.complex_normal((b.total,), seed=4)
+    x = torch.from_numpy(g).cuda()
+    got = b.forward(x).cpu().numpy()
+    for o, p, po in zip(b.offsets, b.plans, oplans):
+        ref = chain.forward(po, g[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny))
+        assert chain.rel_l2(got[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny), ref) <= 1e-11
+
+
+def test_batch_rejects_bad_input(torch, nl):
+    M = next(synth.symplectic_candidates(1))
+    with pytest.raises(nl.NslctError):
+        nl.Batch([nl.Plan(M, 2048, 2048)])
+    with pytest.raises(nl.NslctError):
+        nl.Batch([nl.Plan(M, 64, 64), nl.Plan(M, 64, 64, precision="c128")])

@@ -56,7 +56,9 @@ def _pair(nl, M, Nx, Ny, dx, dy, typ=None, precision="c64"):
 
 
 SHAPES = [(64, 64), (128, 32), (16, 256), (8, 8), (2, 4), (4, 2), (32, 512), (1024, 16), (16, 1024),
-          (256, 128), (2048, 8), (8, 4096)]
+          (256, 128), (2048, 8), (8, 4096),
+          # 3 * 2^k lengths (radix-3 stages), mixed with powers of two
+          (384, 384), (768, 64), (48, 96), (6, 12), (24, 192), (128, 768)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -73,7 +75,7 @@ def test_forward_inverse_match_oracle_c64(torch, nl, shape, typ):
     assert chain.rel_l2(Gi, chain.inverse(po, g)) <= TOL["c64"]
 
 
-@pytest.mark.parametrize("shape", [(64, 64), (16, 32), (8, 128), (256, 256), (2, 2)])
+@pytest.mark.parametrize("shape", [(64, 64), (16, 32), (8, 128), (256, 256), (2, 2), (96, 48), (384, 24)])
 @pytest.mark.parametrize("typ", [1, 2])
 def test_forward_inverse_match_oracle_c128(torch, nl, shape, typ):
     Nx, Ny = shape
