@@ -63,13 +63,18 @@ extern "C" {
 /* Precision of storage and arithmetic. */
 #define NSLCT_C64 0  /* complex64 storage, FP32 butterflies, FP64-exact phases */
 #define NSLCT_C128 1 /* complex128 storage and arithmetic */
+/* complex64 storage, line DFTs on the matrix cores with operands split into
+ * high + low FP16 (or BF16) parts and FP32 accumulation; chirps as NSLCT_C64.
+ * Sides 256 or 4096 (radix-16 stages only). */
+#define NSLCT_C64_SPLIT_F16 2
+#define NSLCT_C64_SPLIT_BF16 3
 
 typedef struct nslct_plan_s* nslct_plan_t;
 typedef struct nslct_batch_s* nslct_batch_t;
 
 /* Planning options; initialise with nslct_opts_default. */
 typedef struct {
-    int precision;         /* NSLCT_C64 (default) or NSLCT_C128 */
+    int precision;         /* NSLCT_C64 (default), NSLCT_C128, NSLCT_C64_SPLIT_F16/BF16 */
     int type_override;     /* 0: trace rule (eq. Reversible08), 1: CM-CC-CM-CC, 2: CC-CM-CC-CM */
     double symplectic_tol; /* accepted max|M J M^T - J|, default 1e-9 */
 } nslct_opts;
@@ -164,6 +169,38 @@ int nslct_inverse_batched(nslct_batch_t batch, const void* in, void* out, void* 
 int nslct_batch_run(nslct_batch_t batch, int direction, int mode, const void* in, void* out, void* stream);
 
 void nslct_batch_destroy(nslct_batch_t batch);
+
+/* Backward sweep for a loss of G = forward(x) (Sec. 6.2: the operator is
+ * unitary, so its adjoint is the inverse chain, eq. CCCMCCCM30).  G is the
+ * forward output and grad_out = dLoss/dRe(G) + j dLoss/dIm(G), both `count`
+ * images.  Runs the inverse chain on G (into `work`) and on grad_out (into
+ * grad_x) together and at each of the five chirp points adds to the device
+ * array sums[15] (caller-zeroed, accumulated over images; must not be read
+ * before the stream reaches this call) the sums of Im(conj(adjoint) signal)
+ * weighted by x^2, x y, y^2.  On return grad_x = L^H grad_out = dLoss/dx.
+ * Sides 8..1024 (2^k) or 48, 96, 192, 384, 768; work, grad_x distinct buffers. */
+int nslct_backward(nslct_plan_t plan, int count, const void* G, const void* grad_out, void* work, void* grad_x,
+                   double* sums, void* stream);
+
+/* Host: the 15 sums of nslct_backward -> dLoss / d(stage-matrix entries),
+ * 12 doubles in the order of nslct_stages.mats (x11, x12, x22 each).  The
+ * derivative of CM(P) g = exp(j phi) g with respect to an entry of P is
+ * j (d phi / d entry) CM(P) g (eq. BasicCM12); CC chirps enter with -B. */
+int nslct_plan_stage_gradient(nslct_plan_t plan, const double sums[15], double grad_stages[12]);
+
+/* Host: out = M expm(J S(theta)), S symmetric 4x4 whose upper triangle,
+ * row by row, is theta (s11, s12, s13, s14, s22, s23, s24, s33, s34, s44);
+ * J S is a general element of the Lie algebra of the ABCD group, so every
+ * output satisfies eq. Intro12 when M does. */
+int nslct_lie_point(const double abcd[16], const double theta[10], double out[16]);
+
+/* Host: d(stage entries)/d(theta) at theta0, jac[12][10] row-major, for
+ * M(theta) = M expm(J S(theta)): central differences of the planner (gauge
+ * re-solved at every point, decomposition type held) with step h in
+ * (0, 1e-2].  Valid where the gauge minimiser moves smoothly (its set of
+ * vanishing stage entries does not change within +-h). */
+int nslct_plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny, double dx, double dy,
+                        const nslct_opts* opts, double h, double jac[12 * 10]);
 
 /* Plain device-to-device copy kernel of `bytes` bytes (multiple of 16): the
  * bandwidth reference the transform is measured against. */

@@ -71,6 +71,11 @@ SIGNATURES = {
     "nslct_inverse_batched": (I, [P, P, P, P]),
     "nslct_batch_run": (I, [P, I, I, P, P, P]),
     "nslct_batch_destroy": (None, [P]),
+    "nslct_backward": (I, [P, I, P, P, P, P, P, P]),
+    "nslct_plan_stage_gradient": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
+    "nslct_lie_point": (I, [ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),
+    "nslct_plan_jacobian": (I, [ctypes.POINTER(D), ctypes.POINTER(D), I, I, D, D, ctypes.POINTER(Opts), D,
+                                ctypes.POINTER(D)]),
     "nslct_last_error": (ctypes.c_char_p, []),
     "nslct_strerror": (ctypes.c_char_p, [I]),
     "nslct_version": (ctypes.c_char_p, []),

@@ -36,6 +36,7 @@
 #include "fft_engine.hpp"
 #include "nslct.h"
 #include "planner.hpp"
+#include "split_fft.hpp"
 
 using namespace nslct;
 
@@ -99,7 +100,35 @@ struct PassArgs {
     int mid_on;            // pointwise product after the first DFT
     ChirpArg pre, mid;
     T scale;               // folded into the pointwise product
+    const cplx<T>* in2;    // backward sweep: second signal (adjoint) ...
+    cplx<T>* out2;
+    double* acc;           // ... and the three gradient sums of this pass
 };
+
+// Sum of three doubles over the workgroup, added atomically to acc[0..2].
+__device__ __forceinline__ void block_sum3(double a0, double a1, double a2, double* acc) {
+    __shared__ double red[3][16];
+    for (int off = 32; off > 0; off >>= 1) {
+        a0 += __shfl_xor(a0, off);
+        a1 += __shfl_xor(a1, off);
+        a2 += __shfl_xor(a2, off);
+    }
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int nw = (blockDim.x + 63) / 64;
+    __syncthreads();
+    if (lane == 0) {
+        red[0][wave] = a0;
+        red[1][wave] = a1;
+        red[2][wave] = a2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double s = 0;
+        for (int k = 0; k < nw; ++k) s += red[threadIdx.x][k];
+        atomicAdd(acc + threadIdx.x, s);
+    }
+    __syncthreads();
+}
 
 // sin/cos of 2 pi * phase, phase in 64-bit fixed-point turns, times scale.
 // FP32: the top 32 bits as a float in [-1/2, 1/2) turns and the hardware
@@ -141,7 +170,7 @@ __device__ __forceinline__ int store_to_fft(int p) {
 // stage a tile of LINES adjacent columns through LDS: the global accesses
 // then cover LINES consecutive samples of each row (coalesced), while each
 // line's FFT work stays with the TPL threads that own it.
-template <typename T, int N, bool COL, int LINES>
+template <typename T, int N, bool COL, int LINES, int NS = 1>
 __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t img_off, cplx<T>* lds_all) {
     constexpr int TPL = LinePlan<N>::TPL;
     using F = LineFFT<T, N, TPL>;
@@ -158,45 +187,56 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
     const bool active = line < nl;
     cplx<T>* lds = lds_all + slot * LL;
     const cplx<T>* __restrict__ tab = twiddles<T>();
-    const cplx<T>* __restrict__ in = a.in + img_off;
-    cplx<T>* __restrict__ out = a.out + img_off;
+    const cplx<T>* ins[2] = {a.in + img_off, NS > 1 ? a.in2 + img_off : nullptr};
+    cplx<T>* outs[2] = {a.out + img_off, NS > 1 ? a.out2 + img_off : nullptr};
 
     cplx<T> w[F::TW];
     F::preload(w, t, tab);
 
     auto pos = [&](int r) { return t + TPL * (r / R0) + (r % R0) * (N / R0); };
 
-    cplx<T> v[E];
-    if constexpr (COL) {
-        // Coalesced tile load: lane -> (column c, row group u).
-        const int c = tid % LINES;
-        const int u = tid / LINES;
-        const bool cok = line0 + c < nl;
+    // NS signals go through identical arithmetic (NS = 2: the forward output
+    // and the adjoint of a backward sweep).
+    cplx<T> v[NS][E];
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-            const int p = u + TPL * k;
-            const int i = a.load_remap ? store_to_fft<N>(p) : p;
-            lds_all[c * LL + lds_pad(i)] = cok ? in[(size_t)p * nl + line0 + c] : cplx<T>{0, 0};
-        }
-        __syncthreads();
+    for (int sg = 0; sg < NS; ++sg) {
+        const cplx<T>* __restrict__ in = ins[sg];
+        if constexpr (COL) {
+            // Coalesced tile load: lane -> (column c, row group u).
+            const int c = tid % LINES;
+            const int u = tid / LINES;
+            const bool cok = line0 + c < nl;
 #pragma unroll
-        for (int r = 0; r < E; ++r) v[r] = lds[lds_pad(pos(r))];
-        __syncthreads();
-    } else {
+            for (int k = 0; k < E; ++k) {
+                const int p = u + TPL * k;
+                const int i = a.load_remap ? store_to_fft<N>(p) : p;
+                lds_all[c * LL + lds_pad(i)] = cok ? in[(size_t)p * nl + line0 + c] : cplx<T>{0, 0};
+            }
+            __syncthreads();
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int p = pos(r);
-            const int src = a.load_remap ? fft_to_store<N>(p) : p;
-            v[r] = active ? in[(size_t)line * N + src] : cplx<T>{0, 0};
+            for (int r = 0; r < E; ++r) v[sg][r] = lds[lds_pad(pos(r))];
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int p = pos(r);
+                const int src = a.load_remap ? fft_to_store<N>(p) : p;
+                v[sg][r] = active ? in[(size_t)line * N + src] : cplx<T>{0, 0};
+            }
         }
     }
 
     const int lc = a.line_centered ? line - nl / 2 : (line >= (nl + 1) / 2 ? line - nl : line);
-    // Chirp exp(j 2 pi phi) with phi = c11 m^2 + c12 m n + c22 n^2 (turns).
-    // Along the line the signed index of register r is e = t + d(r) with d(r)
-    // known at compile time (the wrap to negative indices happens exactly for
-    // the upper half of the first-stage radix), so phi = phi_t + d alpha_t
-    // + d^2 Q with per-thread phi_t, alpha_t; all in exact 64-bit turns.
+    // Signed index along the line of register r: t + d(r) with d(r) known at
+    // compile time (the wrap to negative indices happens exactly for the
+    // upper half of the first-stage radix).
+    auto offs = [&](int r) {
+        const int q = r % R0;
+        return TPL * (r / R0) + (N / R0) * (q < R0 / 2 ? q : q - R0);
+    };
+    // Chirp exp(j 2 pi phi) with phi = c11 m^2 + c12 m n + c22 n^2 (turns):
+    // phi = phi_t + d alpha_t + d^2 Q with per-thread phi_t, alpha_t, all in
+    // exact 64-bit turns.
     auto chirp = [&](const ChirpArg& c, T scale) {
         const uint64_t l64 = (uint64_t)(int64_t)lc;
         const uint64_t A = (COL ? c.c22 : c.c11) * (l64 * l64);
@@ -207,56 +247,89 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
         const uint64_t alpha = Bc + 2 * Q * t64;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-            const int q = r % R0;
-            const int d = TPL * (r / R0) + (N / R0) * (q < R0 / 2 ? q : q - R0);
+            const int d = offs(r);
             const uint64_t ph = phi_t + alpha * (uint64_t)(int64_t)d + Q * (uint64_t)((int64_t)d * d);
-            v[r] = cmul(v[r], turns_cs(ph, scale));
+            const cplx<T> f = turns_cs(ph, scale);
+#pragma unroll
+            for (int sg = 0; sg < NS; ++sg) v[sg][r] = cmul(v[sg][r], f);
+        }
+    };
+    // Backward sweep: at the chirp point, sum Im(conj(adjoint) * signal)
+    // weighted by x^2, x y, y^2 (signed sample indices) into a.acc[0..2].
+    auto gradient_sums = [&]() {
+        if constexpr (NS == 2) {
+            double sxx = 0, sxy = 0, syy = 0;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const double e = (double)(t + offs(r));
+                const double xi = COL ? e : (double)lc;
+                const double yi = COL ? (double)lc : e;
+                const double im = (double)v[1][r].re * (double)v[0][r].im - (double)v[1][r].im * (double)v[0][r].re;
+                sxx += xi * xi * im;
+                sxy += xi * yi * im;
+                syy += yi * yi * im;
+            }
+            block_sum3(sxx, sxy, syy, a.acc);
         }
     };
 
+    if (NS == 2 && !a.mid_on) gradient_sums();
     if (a.pre.on) chirp(a.pre, (T)1);
-    if (a.sign1 < 0)
-        F::template dft<-1>(v, lds, t, w, tab);
-    else
-        F::template dft<+1>(v, lds, t, w, tab);
+#pragma unroll
+    for (int sg = 0; sg < NS; ++sg) {
+        if (a.sign1 < 0)
+            F::template dft<-1>(v[sg], lds, t, w, tab);
+        else
+            F::template dft<+1>(v[sg], lds, t, w, tab);
+    }
     if (a.mid_on) {
+        if (NS == 2) gradient_sums();
         if (a.mid.on) {
             chirp(a.mid, a.scale);
         } else {
 #pragma unroll
-            for (int r = 0; r < E; ++r) v[r] = {v[r].re * a.scale, v[r].im * a.scale};
+            for (int sg = 0; sg < NS; ++sg)
+#pragma unroll
+                for (int r = 0; r < E; ++r) v[sg][r] = {v[sg][r].re * a.scale, v[sg][r].im * a.scale};
         }
     }
     if (a.has_t2) {
-        if (a.sign2 < 0)
-            F::template dft<-1>(v, lds, t, w, tab);
-        else
-            F::template dft<+1>(v, lds, t, w, tab);
+#pragma unroll
+        for (int sg = 0; sg < NS; ++sg) {
+            if (a.sign2 < 0)
+                F::template dft<-1>(v[sg], lds, t, w, tab);
+            else
+                F::template dft<+1>(v[sg], lds, t, w, tab);
+        }
     }
 
-    if constexpr (COL) {
-        __syncthreads();
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int p = pos(r);
-            lds[lds_pad(a.store_remap ? fft_to_store<N>(p) : p)] = v[r];
-        }
-        __syncthreads();
-        const int c = tid % LINES;
-        const int u = tid / LINES;
-        if (line0 + c < nl) {
+    for (int sg = 0; sg < NS; ++sg) {
+        cplx<T>* __restrict__ out = outs[sg];
+        if constexpr (COL) {
+            __syncthreads();
 #pragma unroll
-            for (int k = 0; k < E; ++k) {
-                const int p = u + TPL * k;
-                out[(size_t)p * nl + line0 + c] = lds_all[c * LL + lds_pad(p)];
+            for (int r = 0; r < E; ++r) {
+                const int p = pos(r);
+                lds[lds_pad(a.store_remap ? fft_to_store<N>(p) : p)] = v[sg][r];
             }
-        }
-    } else if (active) {
+            __syncthreads();
+            const int c = tid % LINES;
+            const int u = tid / LINES;
+            if (line0 + c < nl) {
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int p = pos(r);
-            const int dst = a.store_remap ? fft_to_store<N>(p) : p;
-            out[(size_t)line * N + dst] = v[r];
+                for (int k = 0; k < E; ++k) {
+                    const int p = u + TPL * k;
+                    out[(size_t)p * nl + line0 + c] = lds_all[c * LL + lds_pad(p)];
+                }
+            }
+        } else if (active) {
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int p = pos(r);
+                const int dst = a.store_remap ? fft_to_store<N>(p) : p;
+                out[(size_t)line * N + dst] = v[sg][r];
+            }
         }
     }
 }
@@ -407,6 +480,170 @@ PassArgs<T> pass_args(const PlanData& d, int dir, int pass, const void* in, void
     return make_pass_args<T>(d.Nx, d.Ny, c, pass, in, out);
 }
 
+// ------------------------------------------------------ split precision
+// Passes whose line DFTs run on the matrix cores with split half-precision
+// operands (FP32 accumulation); storage complex64, chirps as in the FP32
+// path.  Lines (16^2 or 16^3 long) live in LDS for the whole pass; every
+// element-wise step (chirp, scale) is one sweep over LDS.
+template <int N, bool COL>
+constexpr int split_lines() {
+    return N == 4096 ? (COL ? 2 : 1) : 16;
+}
+
+template <int KIND, int N, bool COL>
+__global__ void __launch_bounds__((split_lines<N, COL>() * N / 16)) nslct_split_pass(PassArgs<float> a) {
+    constexpr int LINES = split_lines<N, COL>();
+    constexpr int THREADS = LINES * N / 16;
+    constexpr int PER = LINES * N / THREADS;  // = 16 elements per thread per sweep
+    constexpr int LL = lds_line_elems<N>();
+    __shared__ cplx<float> lds[LINES * LL];
+    SplitW<KIND> W;  // this lane's A operands (per-lane values, in registers)
+    const int tid = threadIdx.x;
+    const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int line0 = tile * LINES;
+    const int nl = a.nlines;
+    const cplx<float>* __restrict__ in = a.in + (size_t)blockIdx.y * a.img_stride;
+    cplx<float>* __restrict__ out = a.out + (size_t)blockIdx.y * a.img_stride;
+    const cplx<float>* __restrict__ tab = twiddles<float>();
+    W.init(tid % 64);
+
+    // Load into LDS in FFT order.
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = tid + THREADS * k;
+        if constexpr (COL) {
+            const int c = idx % LINES, p = idx / LINES;
+            const int i = a.load_remap ? store_to_fft<N>(p) : p;
+            lds[c * LL + lds_pad(i)] = line0 + c < nl ? in[(size_t)p * nl + line0 + c] : cplx<float>{0, 0};
+        } else {
+            const int ln = idx / N, p = idx % N;
+            const int src = a.load_remap ? fft_to_store<N>(p) : p;
+            lds[ln * LL + lds_pad(p)] = line0 + ln < nl ? in[(size_t)(line0 + ln) * N + src] : cplx<float>{0, 0};
+        }
+    }
+    __syncthreads();
+
+    auto chirp = [&](const ChirpArg& c, float scale) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int idx = tid + THREADS * k;
+            const int ln = idx / N, p = idx % N;
+            const int line = line0 + ln;
+            const int lc = a.line_centered ? line - nl / 2 : (line >= (nl + 1) / 2 ? line - nl : line);
+            const int e = p >= (N + 1) / 2 ? p - N : p;
+            const uint64_t l64 = (uint64_t)(int64_t)lc, e64 = (uint64_t)(int64_t)e;
+            const uint64_t ph = (COL ? c.c22 : c.c11) * (l64 * l64) + c.c12 * (l64 * e64) +
+                                (COL ? c.c11 : c.c22) * (e64 * e64);
+            cplx<float>& v = lds[ln * LL + lds_pad(p)];
+            v = cmul(v, turns_cs(ph, scale));
+        }
+        __syncthreads();
+    };
+
+    if (a.pre.on) chirp(a.pre, 1.f);
+    if (a.sign1 < 0)
+        split_dft<KIND, -1, N, LINES>(lds, W, tab);
+    else
+        split_dft<KIND, +1, N, LINES>(lds, W, tab);
+    if (a.mid_on) chirp(a.mid, a.scale);
+    if (a.has_t2) {
+        if (a.sign2 < 0)
+            split_dft<KIND, -1, N, LINES>(lds, W, tab);
+        else
+            split_dft<KIND, +1, N, LINES>(lds, W, tab);
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = tid + THREADS * k;
+        if constexpr (COL) {
+            const int c = idx % LINES, p = idx / LINES;
+            if (line0 + c < nl)
+                out[(size_t)p * nl + line0 + c] = lds[c * LL + lds_pad(a.store_remap ? store_to_fft<N>(p) : p)];
+        } else {
+            const int ln = idx / N, p = idx % N;
+            if (line0 + ln < nl)
+                out[(size_t)(line0 + ln) * N + (a.store_remap ? fft_to_store<N>(p) : p)] = lds[ln * LL + lds_pad(p)];
+        }
+    }
+}
+
+bool split_size_ok(int n) { return n == 256 || n == 4096; }
+
+template <int KIND, bool COL>
+hipError_t launch_split_n(int N, const PassArgs<float>& a, int count, hipStream_t s) {
+    switch (N) {
+        case 256: {
+            constexpr int L = split_lines<256, COL>();
+            hipLaunchKernelGGL((nslct_split_pass<KIND, 256, COL>), dim3((a.nlines + L - 1) / L, count),
+                               dim3(L * 256 / 16), 0, s, a);
+            return hipGetLastError();
+        }
+        case 4096: {
+            constexpr int L = split_lines<4096, COL>();
+            hipLaunchKernelGGL((nslct_split_pass<KIND, 4096, COL>), dim3((a.nlines + L - 1) / L, count),
+                               dim3(L * 4096 / 16), 0, s, a);
+            return hipGetLastError();
+        }
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------- backward
+// Backward sweep: the inverse chain applied to the forward output G and to
+// the incoming gradient at once, with the gradient sums at every chirp point.
+template <typename T, int N, bool COL, int LINES>
+__global__ void __launch_bounds__(LinePlan<N>::TPL* LINES) nslct_pair_pass(PassArgs<T> a) {
+    __shared__ cplx<T> lds_all[LINES * lds_line_elems<N>()];
+    const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    pass_body<T, N, COL, LINES, 2>(a, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
+}
+
+#define NSLCT_PAIR_SIZES(X) X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+bool pair_size_ok(int n) {
+    switch (n) {
+#define NSLCT_PAIR_OK(v) case v:
+        NSLCT_PAIR_SIZES(NSLCT_PAIR_OK)
+#undef NSLCT_PAIR_OK
+        return true;
+        default:
+            return false;
+    }
+}
+
+template <typename T, bool COL>
+hipError_t launch_pair_n(int N, const PassArgs<T>& a, int count, hipStream_t s) {
+    switch (N) {
+#define NSLCT_PAIR_LAUNCH(v)                                                                     \
+    case v: {                                                                                    \
+        constexpr int L = COL ? col_lines<T, v>() : row_lines<T, v>();                           \
+        hipLaunchKernelGGL((nslct_pair_pass<T, v, COL, L>), dim3((a.nlines + L - 1) / L, count), \
+                           dim3(LinePlan<v>::TPL * L), 0, s, a);                                 \
+        return hipGetLastError();                                                                \
+    }
+        NSLCT_PAIR_SIZES(NSLCT_PAIR_LAUNCH)
+#undef NSLCT_PAIR_LAUNCH
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t run_backward_t(const PlanData& d, int count, const void* G, const void* gout, void* work, void* gx,
+                          double* sums, hipStream_t s) {
+    for (int pass = 0; pass < 5; ++pass) {
+        PassArgs<T> a = pass_args<T>(d, 1, pass, pass == 0 ? G : work, work);
+        a.in2 = (const cplx<T>*)(pass == 0 ? gout : gx);
+        a.out2 = (cplx<T>*)gx;
+        a.acc = sums + 3 * pass;
+        const bool col = (pass == 1 || pass == 3);
+        const hipError_t e = col ? launch_pair_n<T, true>(d.Nx, a, count, s) : launch_pair_n<T, false>(d.Ny, a, count, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // ----------------------------------------------------------------- batched
 // One image of a ragged batch: its sample offset in the packed buffer, its
 // shape, and the chirps of its forward and inverse chains.
@@ -502,8 +739,19 @@ hipError_t launch_pass_typed(const PlanData& d, int dir, int pass, int count, co
     return col ? launch_n<T, true>(d.Nx, a, count, s) : launch_n<T, false>(d.Ny, a, count, s);
 }
 
+template <int KIND, bool COL>
+hipError_t launch_split_n(int N, const PassArgs<float>& a, int count, hipStream_t s);
+
 hipError_t launch_pass(const PlanData& d, int dir, int pass, int count, const void* in, void* out,
                        hipStream_t s) {
+    if (d.precision == NSLCT_C64_SPLIT_F16 || d.precision == NSLCT_C64_SPLIT_BF16) {
+        const PassArgs<float> a = pass_args<float>(d, dir, pass, in, out);
+        const bool col = (pass == 1 || pass == 3);
+        const int N = col ? d.Nx : d.Ny;
+        if (d.precision == NSLCT_C64_SPLIT_F16)
+            return col ? launch_split_n<0, true>(N, a, count, s) : launch_split_n<0, false>(N, a, count, s);
+        return col ? launch_split_n<1, true>(N, a, count, s) : launch_split_n<1, false>(N, a, count, s);
+    }
     return d.precision == NSLCT_C128 ? launch_pass_typed<double>(d, dir, pass, count, in, out, s)
                                      : launch_pass_typed<float>(d, dir, pass, count, in, out, s);
 }
@@ -808,6 +1056,10 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
             delete b;
             return fail(NSLCT_E_ARG, "all plans of a batch must share one precision");
         }
+        if (d.precision != NSLCT_C64 && d.precision != NSLCT_C128) {
+            delete b;
+            return fail(NSLCT_E_UNSUPPORTED, "batches run complex64 or complex128 plans");
+        }
         if (!batch_size_ok(d.Nx) || !batch_size_ok(d.Ny)) {
             delete b;
             return fail(NSLCT_E_SIZE, "batched sides must be one of 64, 128, 192, 256, 384, 512, 768, 1024");
@@ -973,6 +1225,52 @@ int nslct_inverse_batched(nslct_batch_t batch, const void* in, void* out, void* 
 
 void nslct_batch_destroy(nslct_batch_t batch) { delete batch; }
 
+
+int nslct_backward(nslct_plan_t plan, int count, const void* G, const void* grad_out, void* work, void* grad_x,
+                   double* sums, void* stream) {
+    if (!plan) return fail(NSLCT_E_ARG, "null plan");
+    if (count < 1 || count > 65535) return fail(NSLCT_E_ARG, "count must be in [1, 65535]");
+    int rc = check_ptrs(G, grad_out);
+    if (!rc) rc = check_ptrs(work, grad_x);
+    if (rc) return rc;
+    if (!sums || ((uintptr_t)sums & 7)) return fail(NSLCT_E_ARG, "sums must be an 8-byte aligned device pointer");
+    const PlanData& d = plan->d;
+    if (d.precision != NSLCT_C64 && d.precision != NSLCT_C128)
+        return fail(NSLCT_E_UNSUPPORTED, "backward runs complex64 or complex128 plans");
+    if (!pair_size_ok(d.Nx) || !pair_size_ok(d.Ny))
+        return fail(NSLCT_E_SIZE, "backward sides must be 8..1024 (2^k) or 48, 96, 192, 384, 768");
+    if (work == grad_x || work == G || work == grad_out || grad_x == G)
+        return fail(NSLCT_E_ARG, "work and grad_x must be distinct from each other and from G");
+    rc = ensure_device_ready();
+    if (rc) return rc;
+    const hipError_t e = d.precision == NSLCT_C128
+                             ? run_backward_t<double>(d, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream)
+                             : run_backward_t<float>(d, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream);
+    return e == hipSuccess ? NSLCT_OK : fail(NSLCT_E_HIP, std::string("backward launch: ") + hipGetErrorString(e));
+}
+
+int nslct_plan_stage_gradient(nslct_plan_t plan, const double sums[15], double grad_stages[12]) {
+    if (!plan || !sums || !grad_stages) return fail(NSLCT_E_ARG, "null argument");
+    stage_gradient(plan->d, sums, grad_stages);
+    return NSLCT_OK;
+}
+
+int nslct_lie_point(const double abcd[16], const double theta[10], double out[16]) {
+    if (!abcd || !theta || !out) return fail(NSLCT_E_ARG, "null argument");
+    lie_point(abcd, theta, out);
+    return NSLCT_OK;
+}
+
+int nslct_plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny, double dx, double dy,
+                        const nslct_opts* opts, double h, double jac[12 * 10]) {
+    if (!abcd || !theta0 || !jac) return fail(NSLCT_E_ARG, "null argument");
+    nslct_opts o;
+    nslct_opts_default(&o);
+    if (opts) o = *opts;
+    std::string err;
+    const int rc = plan_jacobian(abcd, theta0, Nx, Ny, dx, dy, o, h, jac, &err);
+    return rc ? fail(rc, err) : NSLCT_OK;
+}
 
 const char* nslct_last_error(void) { return g_last_error.c_str(); }
 

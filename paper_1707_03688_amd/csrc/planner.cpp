@@ -492,9 +492,13 @@ int check_common(int Nx, int Ny, double dx, double dy, const nslct_opts& o, std:
         *err = "Nx and Ny must be 2^k in [2, 4096] or 3 * 2^k in [6, 768]";
         return NSLCT_E_SIZE;
     }
-    if (o.precision != NSLCT_C64 && o.precision != NSLCT_C128) {
+    if (o.precision < NSLCT_C64 || o.precision > NSLCT_C64_SPLIT_BF16) {
         *err = "unknown precision";
         return NSLCT_E_ARG;
+    }
+    if (o.precision >= NSLCT_C64_SPLIT_F16 && !((Nx == 256 || Nx == 4096) && (Ny == 256 || Ny == 4096))) {
+        *err = "split-precision sides must be 256 or 4096";
+        return NSLCT_E_SIZE;
     }
     if (o.type_override < 0 || o.type_override > 2) {
         *err = "type_override must be 0, 1 or 2";
@@ -606,6 +610,135 @@ int build_plan_from_stages(const nslct_stages& st, int Nx, int Ny, const nslct_o
     s.symplectic_residual = 0.0;
     fill_chains(out);
     return NSLCT_OK;
+}
+
+namespace {
+
+void mat4_mul(const double* a, const double* b, double* c) {
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double t = 0;
+            for (int k = 0; k < 4; ++k) t += a[4 * i + k] * b[4 * k + j];
+            c[4 * i + j] = t;
+        }
+}
+
+// exp(X) for a 4x4 X: scaling and squaring around a degree-14 Taylor series.
+void mat4_exp(const double* X, double* out) {
+    double nrm = 0;
+    for (int i = 0; i < 4; ++i) {
+        double r = 0;
+        for (int j = 0; j < 4; ++j) r += std::fabs(X[4 * i + j]);
+        nrm = std::max(nrm, r);
+    }
+    int sq = 0;
+    while (nrm > 0.25 && sq < 60) {
+        nrm *= 0.5;
+        ++sq;
+    }
+    const double sc = std::ldexp(1.0, -sq);
+    double Y[16], term[16], tmp[16];
+    for (int i = 0; i < 16; ++i) Y[i] = X[i] * sc;
+    for (int i = 0; i < 16; ++i) out[i] = term[i] = (i % 5 == 0) ? 1.0 : 0.0;
+    for (int k = 1; k <= 14; ++k) {
+        mat4_mul(term, Y, tmp);
+        for (int i = 0; i < 16; ++i) {
+            term[i] = tmp[i] / k;
+            out[i] += term[i];
+        }
+    }
+    for (int k = 0; k < sq; ++k) {
+        mat4_mul(out, out, tmp);
+        std::memcpy(out, tmp, sizeof tmp);
+    }
+}
+
+// J S(theta): S symmetric 4x4 whose upper triangle, row by row, is theta
+// (s11, s12, s13, s14, s22, s23, s24, s33, s34, s44).
+void lie_matrix(const double theta[10], double* X) {
+    double S[16] = {0};
+    int k = 0;
+    for (int r = 0; r < 4; ++r)
+        for (int c = r; c < 4; ++c, ++k) S[4 * r + c] = S[4 * c + r] = theta[k];
+    const double J[16] = {0, 0, 1, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, -1, 0, 0};
+    mat4_mul(J, S, X);
+}
+
+}  // namespace
+
+void lie_point(const double abcd[16], const double theta[10], double* M) {
+    double X[16], E[16];
+    lie_matrix(theta, X);
+    mat4_exp(X, E);
+    mat4_mul(abcd, E, M);
+}
+
+int plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny, double dx, double dy,
+                  const nslct_opts& o, double h, double jac[12 * 10], std::string* err) {
+    if (!(h > 0) || h > 1e-2) {
+        *err = "step must be in (0, 1e-2]";
+        return NSLCT_E_ARG;
+    }
+    double M0[16];
+    lie_point(abcd, theta0, M0);
+    PlanData base;
+    int rc = build_plan(M0, Nx, Ny, dx, dy, o, &base, err);
+    if (rc) return rc;
+    nslct_opts of = o;
+    of.type_override = base.st.type == 0 ? 0 : base.st.type;  // stay on one decomposition type
+    for (int i = 0; i < 10; ++i) {
+        double tp[10], tm[10], Mp[16], Mm[16];
+        for (int k = 0; k < 10; ++k) tp[k] = tm[k] = theta0[k];
+        tp[i] += h;
+        tm[i] -= h;
+        lie_point(abcd, tp, Mp);
+        lie_point(abcd, tm, Mm);
+        PlanData pp, pm;
+        rc = build_plan(Mp, Nx, Ny, dx, dy, of, &pp, err);
+        if (!rc) rc = build_plan(Mm, Nx, Ny, dx, dy, of, &pm, err);
+        if (rc) return rc;
+        if (pp.st.type != pm.st.type) {
+            *err = "decomposition type changes within the difference step";
+            return NSLCT_E_NO_DECOMPOSITION;
+        }
+        for (int m = 0; m < 4; ++m)
+            for (int k = 0; k < 3; ++k) jac[(3 * m + k) * 10 + i] = (pp.st.mats[m][k] - pm.st.mats[m][k]) / (2 * h);
+    }
+    return NSLCT_OK;
+}
+
+void stage_gradient(const PlanData& p, const double sums[15], double g[12]) {
+    // sums[3k..3k+2]: inverse-chain pass k, weights x^2, x y, y^2 in index
+    // units, values scaled by s^2 relative to the unitary chain.
+    const double Nx = p.Nx, Ny = p.Ny;
+    const double s2[5] = {1.0, Nx * Ny, Ny * Ny, Nx * Ny, Ny * Ny};
+    double slot[5][3];
+    for (int k = 0; k < 5; ++k) {
+        const int j = 4 - k;  // forward slot at this point of the inverse chain
+        const bool freq = (j == 1 || j == 3);
+        const double da = freq ? p.st.dwx : p.st.dx, db = freq ? p.st.dwy : p.st.dy;
+        // d loss / d p = Re sum conj(r) i (d phi / d p) u = -(d phi / d p) Im(conj(r) u)
+        slot[j][0] = -0.5 * da * da * sums[3 * k + 0] / s2[k];
+        slot[j][1] = -da * db * sums[3 * k + 1] / s2[k];
+        slot[j][2] = -0.5 * db * db * sums[3 * k + 2] / s2[k];
+    }
+    auto put = [&](int m, int j, double sg) {
+        for (int k = 0; k < 3; ++k) g[3 * m + k] = sg * slot[j][k];
+    };
+    for (int k = 0; k < 12; ++k) g[k] = 0;
+    if (p.st.type == 1) {  // {P1, B', P3, H} = {S4, -C3, S2, -C1}
+        put(0, 4, 1.0);
+        put(1, 3, -1.0);
+        put(2, 2, 1.0);
+        put(3, 1, -1.0);
+    } else if (p.st.type == 2) {  // {H1, Q1, B1', Q3} = {-C3, S2, -C1, S0}
+        put(0, 3, -1.0);
+        put(1, 2, 1.0);
+        put(2, 1, -1.0);
+        put(3, 0, 1.0);
+    } else {
+        put(0, 0, 1.0);
+    }
 }
 
 bool box_check(const PlanData& p, double frac) {

@@ -41,6 +41,14 @@ int build_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, cons
                PlanData* out, std::string* err);
 int build_plan_from_stages(const nslct_stages& st, int Nx, int Ny, const nslct_opts& o,
                            PlanData* out, std::string* err);
+// M expm(J S(theta)) (10 Lie coordinates theta).
+void lie_point(const double abcd[16], const double theta[10], double* M);
+// d(stage entries)/d(theta) at theta0 for M(theta) = M expm(J S(theta)),
+// central differences of the planner with step h.
+int plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny, double dx, double dy,
+                  const nslct_opts& o, double h, double jac[12 * 10], std::string* err);
+// Raw backward sums (15) -> d loss / d(stage entries) (12, order of st.mats).
+void stage_gradient(const PlanData& p, const double sums[15], double g[12]);
 // Phase-space box check (eqs. HA12-HA20) with the input in fraction `frac`.
 bool box_check(const PlanData& p, double frac);
 

@@ -145,3 +145,38 @@ def test_plan_from_stages_roundtrip_and_box(nl):
     big = nl.Plan.from_stages(1, [m * 0 for m in mats[:1]] + [np.eye(2) * 50] + [m * 0 for m in mats[2:]],
                               32, 32, 0.5, 0.5)
     assert not big.box_check(0.5)
+
+
+def test_lie_point_and_plan_jacobian_against_oracle(nl):
+    """nslct_lie_point = M expm(J S(theta)) (scipy expm), and the planner's
+    d(stage entries)/d(theta) agrees with central differences of the oracle's
+    own gauge search (two independent minimisers of eq. HA24)."""
+    from scipy.linalg import expm
+    from paper_1707_03688_amd import autograd as ag
+    J = np.block([[np.zeros((2, 2)), np.eye(2)], [-np.eye(2), np.zeros((2, 2))]])
+
+    def S(th):
+        out = np.zeros((4, 4))
+        k = 0
+        for r in range(4):
+            for c in range(r, 4):
+                out[r, c] = out[c, r] = th[k]
+                k += 1
+        return out
+
+    M0 = next(synth.symplectic_candidates(5))
+    th0 = np.random.default_rng(1).normal(0, 0.05, 10)
+    assert np.max(np.abs(ag.lie_point(M0, th0) - M0 @ expm(J @ S(th0)))) <= 1e-13
+    typ = oplan.plan(M0 @ expm(J @ S(th0)), 32, 24, 0.45, 0.6).typ
+    jac = ag.plan_jacobian(M0, th0, 32, 24, 0.45, 0.6, type_override=typ)
+    h = 1e-4
+    ref = np.zeros((12, 10))
+    for i in range(10):
+        e = np.zeros(10)
+        e[i] = h
+        pp = oplan.plan(M0 @ expm(J @ S(th0 + e)), 32, 24, 0.45, 0.6, typ=typ)
+        pm = oplan.plan(M0 @ expm(J @ S(th0 - e)), 32, 24, 0.45, 0.6, typ=typ)
+        for m in range(4):
+            for k, (a, b) in enumerate([(0, 0), (0, 1), (1, 1)]):
+                ref[3 * m + k, i] = (pp.mats[m][a, b] - pm.mats[m][a, b]) / (2 * h)
+    assert np.max(np.abs(jac - ref)) <= 1e-6 * max(1.0, np.max(np.abs(ref)))
