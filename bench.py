@@ -111,6 +111,48 @@ def bench_batched(nl, torch, synth, np, count=256, seed=2):
             "autotuned_wg_per_cu": b.mult}
 
 
+def bench_split(nl, torch, synth, np, count=8, N=4096, reps=3):
+    """`count` images of N x N, each with its own seeded ABCD (seed 3): the
+    FP32 path against the split FP16 / BF16 matrix-core paths, time per
+    batch and the worst per-image relative L2 error against the complex128
+    path on the same input."""
+    d = math.sqrt(2 * math.pi / N)
+    cands = synth.symplectic_candidates(3)
+    precs = ["c64", "c64_split_f16", "c64_split_bf16"]
+    out = {p: {"s": 0.0, "worst_rel_l2": 0.0} for p in precs}
+    y = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+    for b in range(count):
+        M = next(cands)
+        p64 = nl.Plan(M, N, N, d, d, precision="c128")
+        st = p64.stages()
+        x = torch.from_numpy(synth.complex_normal((N, N), seed=100 + b)).cuda()
+        ref = p64.forward(x)
+        xc = x.to(torch.complex64)
+        del x
+        for prec in precs:
+            p = nl.Plan.from_stages(st["type"], st["mats"], N, N, d, d, prec)
+            p.forward(xc, out=y)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(torch.cuda.current_stream())
+            for _ in range(reps):
+                p.forward(xc, out=y)
+            e1.record(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            out[prec]["s"] += e0.elapsed_time(e1) * 1e-3 / reps
+            err = (torch.linalg.vector_norm(y.to(torch.complex128) - ref)
+                   / torch.linalg.vector_norm(ref)).item()
+            out[prec]["worst_rel_l2"] = max(out[prec]["worst_rel_l2"], err)
+        del ref, xc
+    res = {"images": count, "N": N}
+    for prec in precs:
+        res[prec] = {"ms_per_batch": out[prec]["s"] * 1e3, "NsLCT_per_s": count / out[prec]["s"],
+                     "worst_rel_l2_vs_c128": out[prec]["worst_rel_l2"]}
+    for prec in precs[1:]:
+        res[prec]["speedup_vs_c64"] = out["c64"]["s"] / out[prec]["s"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +161,7 @@ def main():
     ap.add_argument("--ring", type=int, default=48, help="distinct in/out image pairs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--batched", type=int, default=1, help="also time the ragged batched workload")
+    ap.add_argument("--split", type=int, default=1, help="also time the split-precision 8 x 4096^2 leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched and "
@@ -207,6 +250,7 @@ def main():
     del x8, y8
 
     batched = bench_batched(nl, torch, synth, np) if args.batched else None
+    split = bench_split(nl, torch, synth, np) if args.split else None
 
     G = outs[(K - 1) % R].cpu().numpy()
     result = {
@@ -239,6 +283,8 @@ def main():
     }
     if batched:
         result["batched_ragged"] = batched
+    if split:
+        result["split_precision_4096"] = split
     if not args.no_cpu:
         rate, threads, runs, ref = cpu_baseline((st["type"], st["mats"], N, d), g)
         from oracle import chain

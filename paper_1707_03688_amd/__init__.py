@@ -16,7 +16,7 @@ from ._lib import (NSLCT_C64, NSLCT_C128, NslctError, Stages, lib, check)  # noq
 
 __all__ = ["Plan", "Batch", "NslctError", "lib", "device_copy", "NSLCT_C64", "NSLCT_C128"]
 
-_PRECISION = {"c64": NSLCT_C64, "c128": NSLCT_C128}
+_PRECISION = {"c64": NSLCT_C64, "c128": NSLCT_C128, "c64_split_f16": 2, "c64_split_bf16": 3}
 
 
 def _torch():
@@ -105,7 +105,7 @@ class Plan:
     # ------------------------------------------------------------- transforms
     def _check_tensor(self, x):
         torch = _torch()
-        want = torch.complex64 if self.precision == "c64" else torch.complex128
+        want = torch.complex128 if self.precision == "c128" else torch.complex64
         if x.dtype != want:
             raise TypeError(f"expected {want}, got {x.dtype}")
         if not x.is_cuda:
@@ -187,7 +187,7 @@ class Batch:
 
     def _check(self, x):
         torch = _torch()
-        want = torch.complex64 if self.precision == "c64" else torch.complex128
+        want = torch.complex128 if self.precision == "c128" else torch.complex64
         if x.dtype != want or not x.is_cuda or not x.is_contiguous() or x.numel() != self.total:
             raise ValueError(f"expected a contiguous {want} GPU tensor of {self.total} samples")
 
