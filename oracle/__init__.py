@@ -26,10 +26,13 @@ linear canonical transform based on CM-CC-CM-CC decomposition":
 * ``direct``     -- the direct method (eq. Intro32) and the closed-form
   continuous NsLCT (eq. Intro08) of a Gaussian.
 * ``sampling``   -- the phase-space growth predicate (eqs. HA12-HA20).
+* ``fast``       -- the reduced decompositions: CM-CC-CM for symmetric B
+  (Sec. 4.1, eq. Bsym12) and the LC-NsDLCT with a rank-one gauge (Sec.
+  4.2.2, eqs. LC04-LC12).
 
 Pins (checked by ``tests/test_oracle_*.py``) tie every function to something
 other than itself; see the test docstrings.
 """
-from . import symplectic, ops, gauge, chain, dense, direct, sampling  # noqa: F401
+from . import symplectic, ops, gauge, chain, dense, direct, sampling, fast  # noqa: F401
 from . import plan  # noqa: F401
 from .plan import Plan, plan_from_stages  # noqa: F401
