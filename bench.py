@@ -28,8 +28,12 @@ if ROOT not in sys.path:
 
 METRIC = "NsLCT/s @1024² c64 + %HBM peak; split-prec vs FP32 plain at relL2≤1e-4"
 HBM_PEAK_GBPS = 8000.0
-PASS_NAMES = ["rows: [CM] FFT_y", "cols: FFT_x CM IFFT_x", "rows: IFFT_y CM FFT_y",
-              "cols: FFT_x CM IFFT_x", "rows: IFFT_y CM"]
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by the
+# copy-kernel calibration (profiles/nslct_pass_1024_c64_forward.md).  Set to
+# None whenever the kernels change until the counters are taken again.
+TRAFFIC_BYTES = {"rows": 16969 * 1024, "cols": 17020 * 1024}
+KERNEL_NAMES = {"rows": "nslct_pass<float, 1024, false, 4> (passes 0, 2, 4: row lines)",
+                "cols": "nslct_pass<float, 1024, true, 4> (passes 1, 3: column lines)"}
 
 
 def draw_matrix(seed: int, N: int, d: float, nl):
@@ -153,6 +157,58 @@ def bench_split(nl, torch, synth, np, count=8, N=4096, reps=3):
     return res
 
 
+def bench_backward(nl, torch, synth, np, count=32, N=512, reps=10):
+    """One training step of loss = ||NsDLCT_M(theta)(x) - y||^2 on `count`
+    images of N x N (y: the transform under a perturbed matrix): forward,
+    loss, backward through the adjoint kernel.  Reports the device time of
+    forward + adjoint kernels (HIP events) and the whole step including the
+    host-side planning (gauge re-solve for M(theta) and its Jacobian)."""
+    from paper_1707_03688_amd import autograd as ag
+    d = math.sqrt(2 * math.pi / N)
+    M0 = next(synth.symplectic_candidates(4))
+    rng = np.random.default_rng(4)
+    theta_star = rng.normal(0.0, 0.05, size=10)
+    x = torch.from_numpy(synth.complex_normal((count, N, N), seed=4)).to(torch.complex64).cuda()
+    pstar = nl.Plan(ag.lie_point(M0, theta_star), N, N, d, d, symplectic_tol=1e-8)
+    y = pstar.forward(x)
+    p0 = nl.Plan(M0, N, N, d, d, symplectic_tol=1e-8)
+    G = p0.forward(x)
+    gout = 2 * (G - y)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        p0.forward(x, out=G)
+        ag.backward_sums(p0, G, gout)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        p0.forward(x, out=G)
+        ag.backward_sums(p0, G, gout)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dev_s = e0.elapsed_time(e1) * 1e-3 / reps
+
+    def step():
+        xg = x.clone().requires_grad_(True)
+        theta = torch.zeros(10, dtype=torch.float64, requires_grad=True)
+        loss = (ag.nsdlct(xg, theta, M0, d, d) - y).abs().pow(2).sum()
+        loss.backward()
+        return loss
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    full_s = (time.perf_counter() - t0) / 2
+    return {"images": count, "N": N, "device_fwd_bwd_ms": dev_s * 1e3, "device_steps_per_s": 1 / dev_s,
+            "device_pct_hbm_peak": 240.0 * count * N * N / dev_s / 1e9 / HBM_PEAK_GBPS * 100,
+            "full_step_ms": full_s * 1e3,
+            "note": "device = forward (5 passes) + paired adjoint sweep (5 passes, two signals); "
+                    "bytes 80 + 160 B/px; full step adds torch loss ops and host planning"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +218,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--batched", type=int, default=1, help="also time the ragged batched workload")
     ap.add_argument("--split", type=int, default=1, help="also time the split-precision 8 x 4096^2 leg")
+    ap.add_argument("--conc", type=int, default=1, help="also time 8 transforms per launch")
+    ap.add_argument("--backward", type=int, default=1, help="also time the 32 x 512^2 fwd+bwd step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched and "
@@ -200,22 +258,28 @@ def main():
     sec = t1 - t0
     value = K / sec
 
-    # Per-kernel durations: the same K transforms, each pass bracketed by HIP
-    # events recorded on the launch stream.
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
-    torch.cuda.synchronize()
-    for i in range(K):
-        a, b = ins[i % R], outs[i % R]
-        ev[i][0].record(stream)
-        for p in range(5):
-            plan.launch_pass(0, p, a if p == 0 else b, b)
-            ev[i][p + 1].record(stream)
-    torch.cuda.synchronize()
-    pass_ms = [float(np.mean([ev[i][p].elapsed_time(ev[i][p + 1]) for i in range(K)])) for p in range(5)]
-    dom = int(np.argmax(pass_ms))
+    # Per-kernel durations: each pass launched K times back to back over the
+    # ring (HIP events recorded on the launch stream around the K launches).
+    # Passes 0, 2, 4 run the row kernel and passes 1, 3 the column kernel;
+    # a kernel's average launch duration is the mean over its passes.
+    pass_ms = []
+    for p in range(5):
+        for i in range(3):
+            plan.launch_pass(0, p, ins[i % R] if p == 0 else outs[i % R], outs[i % R])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(K):
+            plan.launch_pass(0, p, ins[i % R] if p == 0 else outs[i % R], outs[i % R])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pass_ms.append(e0.elapsed_time(e1) / K)
+    kernels = {"rows": [0, 2, 4], "cols": [1, 3]}
+    kern_ms = {k: float(np.mean([pass_ms[p] for p in ps])) for k, ps in kernels.items()}
+    dom = max(kernels, key=lambda k: kern_ms[k] * len(kernels[k]))
     px = N * N
     bytes_per_launch = 16.0 * px  # one read + one write of complex64
-    achieved = bytes_per_launch / (pass_ms[dom] * 1e-3) / 1e9
+    achieved = bytes_per_launch / (kern_ms[dom] * 1e-3) / 1e9
 
     # Copy-kernel reference bandwidth on the same buffers.
     src = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.complex64, device="cuda")
@@ -234,25 +298,29 @@ def main():
 
     # Independent single-image transforms processed 8 per launch (same kernels,
     # grid.y = 8): the throughput regime, reported beside the sequential value.
-    x8 = torch.stack(ins[:8]).contiguous()
-    y8 = torch.empty_like(x8)
-    for _ in range(3):
-        plan.forward(x8, out=y8)
-    torch.cuda.synchronize()
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = max(10, K // 8)
-    c0.record(stream)
-    for _ in range(reps):
-        plan.forward(x8, out=y8)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    conc = 8 * reps / (c0.elapsed_time(c1) * 1e-3)
-    del x8, y8
+    conc = None
+    if args.conc:
+        x8 = torch.stack(ins[:8]).contiguous()
+        y8 = torch.empty_like(x8)
+        for _ in range(3):
+            plan.forward(x8, out=y8)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(10, K // 8)
+        c0.record(stream)
+        for _ in range(reps):
+            plan.forward(x8, out=y8)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        conc = 8 * reps / (c0.elapsed_time(c1) * 1e-3)
+        del x8, y8
 
     batched = bench_batched(nl, torch, synth, np) if args.batched else None
     split = bench_split(nl, torch, synth, np) if args.split else None
+    bwd = bench_backward(nl, torch, synth, np) if args.backward else None
 
-    G = outs[(K - 1) % R].cpu().numpy()
+    plan.forward(ins[0], out=outs[0])
+    G = outs[0].cpu().numpy()
     result = {
         "metric": METRIC,
         "value": value,
@@ -271,20 +339,24 @@ def main():
                    "Nx": N, "Ny": N, "precision": "c64", "type": st["type"], "draw": draw,
                    "ring_pairs": R, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": f"pass {dom} ({PASS_NAMES[dom]})"},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": TRAFFIC_BYTES[dom],
+                     "kernel": KERNEL_NAMES[dom], "avg_launch_us": kern_ms[dom] * 1e3,
+                     "launches_per_transform": len(kernels[dom])},
         "pass_us": [round(v * 1e3, 3) for v in pass_ms],
         "hbm_effective_GBps": 80.0 * px * value / 1e9,
         "pct_hbm_peak": 80.0 * px * value / 1e9 / HBM_PEAK_GBPS * 100,
         "copy_kernel_GBps": copy_gbps,
-        "concurrent8": {"value": conc, "unit": "NsLCT/s",
-                        "pct_hbm_peak": 80.0 * px * conc / 1e9 / HBM_PEAK_GBPS * 100,
-                        "note": "8 independent 1024x1024 transforms per launch (grid.y = 8)"},
     }
+    if conc:
+        result["concurrent8"] = {"value": conc, "unit": "NsLCT/s",
+                                 "pct_hbm_peak": 80.0 * px * conc / 1e9 / HBM_PEAK_GBPS * 100,
+                                 "note": "8 independent 1024x1024 transforms per launch (grid.y = 8)"}
     if batched:
         result["batched_ragged"] = batched
     if split:
         result["split_precision_4096"] = split
+    if bwd:
+        result["fwd_bwd_512"] = bwd
     if not args.no_cpu:
         rate, threads, runs, ref = cpu_baseline((st["type"], st["mats"], N, d), g)
         from oracle import chain

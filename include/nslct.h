@@ -75,7 +75,11 @@ typedef struct nslct_batch_s* nslct_batch_t;
 /* Planning options; initialise with nslct_opts_default. */
 typedef struct {
     int precision;         /* NSLCT_C64 (default), NSLCT_C128, NSLCT_C64_SPLIT_F16/BF16 */
-    int type_override;     /* 0: trace rule (eq. Reversible08), 1: CM-CC-CM-CC, 2: CC-CM-CC-CM */
+    int type_override;     /* 0: trace rule (eq. Reversible08), 1: CM-CC-CM-CC, 2: CC-CM-CC-CM,
+                              3: CM-CC-CM (Sec. 4.1, B symmetric and invertible),
+                              4: LC-NsDLCT with H = (h,0;0,0) (Sec. 4.2.2, eq. LC08),
+                              5: LC-NsDLCT with H = (0,0;0,h) (eq. LC10),
+                              6: LC-NsDLCT, the form with the smaller eq. HA24 objective */
     double symplectic_tol; /* accepted max|M J M^T - J|, default 1e-9 */
 } nslct_opts;
 
@@ -83,7 +87,14 @@ typedef struct {
  *   type 1: mats = {P1, B', P3, H}    -> CM(P1) CC(B') CM(P3) CC(H)
  *   type 2: mats = {H1, Q1, B1', Q3}  -> CC(H1) CM(Q1) CC(B1') CM(Q3)
  *   type 0: mats[0] = C (pure chirp multiplication, B = 0, A = D = I)
- * Each symmetric 2x2 matrix is stored as (x11, x12, x22). */
+ *   type 3: mats = {P1, B, P3, 0}     -> CM(P1) CC(B) CM(P3)        (eq. Bsym12)
+ *   type 4: mats = {P1, B', P3, H}, H = (h, 0; 0, 0), LC along x   (eq. LC12)
+ *   type 5: mats = {P1, B', P3, H}, H = (0, 0; 0, h), LC along y
+ * Each symmetric 2x2 matrix is stored as (x11, x12, x22).  Types 3-5 have one
+ * 2D CC; their overall constant is +1 like the two-CC chains' (the paper's
+ * DFT constants taken literally would give -1 there), and their 1D CC uses
+ * the unitary 1D DFT pair (a 1D CC with h = 0 is the identity).  They run as
+ * three passes (48 B per sample for complex64) on the single-image path. */
 typedef struct {
     int type;
     double mats[4][3];
@@ -134,11 +145,16 @@ int nslct_forward_many(nslct_plan_t plan, int count, const void* in, void* out, 
 int nslct_inverse_many(nslct_plan_t plan, int count, const void* in, void* out, void* stream);
 
 /* One of the five fused passes of the forward (direction 0) or inverse
- * (direction 1) chain, pass = 0..4, on `count` images: pass 0 reads `in`,
- * every pass writes `out`; chaining passes 0..4 with in = out after the first
- * equals nslct_forward_many / nslct_inverse_many.  For profiling. */
+ * (direction 1) chain, pass = 0 .. nslct_plan_passes - 1, on `count` images:
+ * pass 0 reads `in`, every pass writes `out`; chaining all passes with
+ * in = out after the first equals nslct_forward_many / nslct_inverse_many.
+ * For profiling. */
 int nslct_launch_pass(nslct_plan_t plan, int direction, int pass, int count,
                       const void* in, void* out, void* stream);
+
+/* Number of passes of the single-image path of `plan`: 3 for the reduced
+ * chains (types 3-5) in complex64 / complex128, else 5.  Host only. */
+int nslct_plan_passes(nslct_plan_t plan, int* npasses);
 
 /* Ragged batch: `count` plans (each with its own matrix and size) over one
  * packed buffer in which image i occupies samples [off_i, off_i + Nx_i Ny_i),

@@ -97,6 +97,12 @@ class Plan:
                 "dx": st.dx, "dy": st.dy, "dwx": st.dwx, "dwy": st.dwy,
                 "Nx": getattr(self, "Nx", None), "Ny": getattr(self, "Ny", None)}
 
+    def passes(self) -> int:
+        """Passes of the single-image path (3 for the reduced chains, else 5)."""
+        n = ctypes.c_int()
+        check(lib.nslct_plan_passes(self._h, ctypes.byref(n)))
+        return n.value
+
     def box_check(self, frac: float = 0.5) -> bool:
         ok = ctypes.c_int()
         check(lib.nslct_plan_box_check(self._h, float(frac), ctypes.byref(ok)))

@@ -100,6 +100,10 @@ struct PassArgs {
     int mid_on;            // pointwise product after the first DFT
     ChirpArg pre, mid;
     T scale;               // folded into the pointwise product
+    int post_on;           // reduced schedules (X3 kernels): pointwise product
+    int sign3;             // after the second DFT, then a third DFT
+    ChirpArg post;
+    T scale2;
     const cplx<T>* in2;    // backward sweep: second signal (adjoint) ...
     cplx<T>* out2;
     double* acc;           // ... and the three gradient sums of this pass
@@ -170,7 +174,7 @@ __device__ __forceinline__ int store_to_fft(int p) {
 // stage a tile of LINES adjacent columns through LDS: the global accesses
 // then cover LINES consecutive samples of each row (coalesced), while each
 // line's FFT work stays with the TPL threads that own it.
-template <typename T, int N, bool COL, int LINES, int NS = 1>
+template <typename T, int N, bool COL, int LINES, int NS = 1, bool X3 = false>
 __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t img_off, cplx<T>* lds_all) {
     constexpr int TPL = LinePlan<N>::TPL;
     using F = LineFFT<T, N, TPL>;
@@ -234,9 +238,12 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
         const int q = r % R0;
         return TPL * (r / R0) + (N / R0) * (q < R0 / 2 ? q : q - R0);
     };
-    // Chirp exp(j 2 pi phi) with phi = c11 m^2 + c12 m n + c22 n^2 (turns):
-    // phi = phi_t + d alpha_t + d^2 Q with per-thread phi_t, alpha_t, all in
-    // exact 64-bit turns.
+    // Chirp exp(j 2 pi phi) with phi = c11 m^2 + c12 m n + c22 n^2 (turns),
+    // all in exact 64-bit turns: phi = phi_t + d alpha_t + d^2 Q for the
+    // register at signed offset d from t.  The registers i R0 .. i R0 + R0 - 1
+    // sit at d = TPL i + M s, s = -R0/2 .. R0/2 - 1 (M = N / R0), so along s
+    // phi is advanced by exact second-order differences (two 64-bit adds per
+    // sample).
     auto chirp = [&](const ChirpArg& c, T scale) {
         const uint64_t l64 = (uint64_t)(int64_t)lc;
         const uint64_t A = (COL ? c.c22 : c.c11) * (l64 * l64);
@@ -245,13 +252,23 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
         const uint64_t t64 = (uint64_t)t;
         const uint64_t phi_t = A + Bc * t64 + Q * (t64 * t64);
         const uint64_t alpha = Bc + 2 * Q * t64;
+        constexpr int M = N / R0;
+        const uint64_t dd = Q * (uint64_t)(2 * M * M);
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int d = offs(r);
-            const uint64_t ph = phi_t + alpha * (uint64_t)(int64_t)d + Q * (uint64_t)((int64_t)d * d);
-            const cplx<T> f = turns_cs(ph, scale);
+        for (int i = 0; i < E / R0; ++i) {
+            constexpr int h = R0 / 2;
+            const int64_t d0 = (int64_t)TPL * i - (int64_t)M * h;
+            uint64_t ph = phi_t + alpha * (uint64_t)d0 + Q * (uint64_t)(d0 * d0);
+            uint64_t df = alpha * (uint64_t)M + Q * (uint64_t)(2 * d0 * M + (int64_t)M * M);
 #pragma unroll
-            for (int sg = 0; sg < NS; ++sg) v[sg][r] = cmul(v[sg][r], f);
+            for (int sidx = 0; sidx < R0; ++sidx) {
+                const int q = sidx < h ? sidx + h : sidx - h;  // register of s = sidx - h
+                const cplx<T> f = turns_cs(ph, scale);
+#pragma unroll
+                for (int sg = 0; sg < NS; ++sg) v[sg][i * R0 + q] = cmul(v[sg][i * R0 + q], f);
+                ph += df;
+                df += dd;
+            }
         }
     };
     // Backward sweep: at the chirp point, sum Im(conj(adjoint) * signal)
@@ -302,6 +319,26 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
                 F::template dft<+1>(v[sg], lds, t, w, tab);
         }
     }
+    if constexpr (X3) {
+        // Reduced schedules: a second pointwise product and a third DFT.
+        if (a.post_on) {
+            if (a.post.on) {
+                chirp(a.post, a.scale2);
+            } else {
+#pragma unroll
+                for (int sg = 0; sg < NS; ++sg)
+#pragma unroll
+                    for (int r = 0; r < E; ++r) v[sg][r] = {v[sg][r].re * a.scale2, v[sg][r].im * a.scale2};
+            }
+        }
+#pragma unroll
+        for (int sg = 0; sg < NS; ++sg) {
+            if (a.sign3 < 0)
+                F::template dft<-1>(v[sg], lds, t, w, tab);
+            else
+                F::template dft<+1>(v[sg], lds, t, w, tab);
+        }
+    }
 
 #pragma unroll
     for (int sg = 0; sg < NS; ++sg) {
@@ -340,11 +377,11 @@ constexpr size_t lds_bytes(int lines) {
 }
 
 // Single-plan pass: blockIdx.x = line tile, blockIdx.y = image.
-template <typename T, int N, bool COL, int LINES>
+template <typename T, int N, bool COL, int LINES, bool X3 = false>
 __global__ void __launch_bounds__(LinePlan<N>::TPL* LINES) nslct_pass(PassArgs<T> a) {
     __shared__ cplx<T> lds_all[LINES * lds_line_elems<N>()];
     const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    pass_body<T, N, COL, LINES>(a, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
+    pass_body<T, N, COL, LINES, 1, X3>(a, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
 }
 
 template <typename T, int N>
@@ -358,39 +395,39 @@ constexpr int col_lines() {
     return c > cmin ? c : cmin;
 }
 
-template <typename T, int N, bool COL>
+template <typename T, int N, bool COL, bool X3 = false>
 hipError_t launch_t(const PassArgs<T>& a, int count, hipStream_t s) {
     constexpr int L = COL ? col_lines<T, N>() : row_lines<T, N>();
     static_assert(L * lds_line_elems<N>() * sizeof(cplx<T>) <= 160 * 1024, "LDS budget");
     dim3 grid((a.nlines + L - 1) / L, count);
     dim3 block(LinePlan<N>::TPL * L);
-    hipLaunchKernelGGL((nslct_pass<T, N, COL, L>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((nslct_pass<T, N, COL, L, X3>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, bool COL>
+template <typename T, bool COL, bool X3 = false>
 hipError_t launch_n(int N, const PassArgs<T>& a, int count, hipStream_t s) {
     switch (N) {
-        case 2: return launch_t<T, 2, COL>(a, count, s);
-        case 6: return launch_t<T, 6, COL>(a, count, s);
-        case 12: return launch_t<T, 12, COL>(a, count, s);
-        case 24: return launch_t<T, 24, COL>(a, count, s);
-        case 48: return launch_t<T, 48, COL>(a, count, s);
-        case 96: return launch_t<T, 96, COL>(a, count, s);
-        case 192: return launch_t<T, 192, COL>(a, count, s);
-        case 384: return launch_t<T, 384, COL>(a, count, s);
-        case 768: return launch_t<T, 768, COL>(a, count, s);
-        case 4: return launch_t<T, 4, COL>(a, count, s);
-        case 8: return launch_t<T, 8, COL>(a, count, s);
-        case 16: return launch_t<T, 16, COL>(a, count, s);
-        case 32: return launch_t<T, 32, COL>(a, count, s);
-        case 64: return launch_t<T, 64, COL>(a, count, s);
-        case 128: return launch_t<T, 128, COL>(a, count, s);
-        case 256: return launch_t<T, 256, COL>(a, count, s);
-        case 512: return launch_t<T, 512, COL>(a, count, s);
-        case 1024: return launch_t<T, 1024, COL>(a, count, s);
-        case 2048: return launch_t<T, 2048, COL>(a, count, s);
-        case 4096: return launch_t<T, 4096, COL>(a, count, s);
+        case 2: return launch_t<T, 2, COL, X3>(a, count, s);
+        case 6: return launch_t<T, 6, COL, X3>(a, count, s);
+        case 12: return launch_t<T, 12, COL, X3>(a, count, s);
+        case 24: return launch_t<T, 24, COL, X3>(a, count, s);
+        case 48: return launch_t<T, 48, COL, X3>(a, count, s);
+        case 96: return launch_t<T, 96, COL, X3>(a, count, s);
+        case 192: return launch_t<T, 192, COL, X3>(a, count, s);
+        case 384: return launch_t<T, 384, COL, X3>(a, count, s);
+        case 768: return launch_t<T, 768, COL, X3>(a, count, s);
+        case 4: return launch_t<T, 4, COL, X3>(a, count, s);
+        case 8: return launch_t<T, 8, COL, X3>(a, count, s);
+        case 16: return launch_t<T, 16, COL, X3>(a, count, s);
+        case 32: return launch_t<T, 32, COL, X3>(a, count, s);
+        case 64: return launch_t<T, 64, COL, X3>(a, count, s);
+        case 128: return launch_t<T, 128, COL, X3>(a, count, s);
+        case 256: return launch_t<T, 256, COL, X3>(a, count, s);
+        case 512: return launch_t<T, 512, COL, X3>(a, count, s);
+        case 1024: return launch_t<T, 1024, COL, X3>(a, count, s);
+        case 2048: return launch_t<T, 2048, COL, X3>(a, count, s);
+        case 4096: return launch_t<T, 4096, COL, X3>(a, count, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -742,8 +779,54 @@ hipError_t launch_pass_typed(const PlanData& d, int dir, int pass, int count, co
 template <int KIND, bool COL>
 hipError_t launch_split_n(int N, const PassArgs<float>& a, int count, hipStream_t s);
 
+// Passes of the single-image path: the three-pass schedule of a reduced
+// chain (CM-CC-CM, LC) in c64 / c128, else the five-pass chain.
+int plan_passes(const PlanData& d) {
+    const bool split = d.precision == NSLCT_C64_SPLIT_F16 || d.precision == NSLCT_C64_SPLIT_BF16;
+    return (!split && d.prog[0].npass > 0) ? d.prog[0].npass : 5;
+}
+
+template <typename T>
+PassArgs<T> program_args(const PlanData& d, int dir, int k, const void* in, void* out) {
+    const ProgPass& q = d.prog[dir].p[k];
+    PassArgs<T> a{};
+    a.in = (const cplx<T>*)in;
+    a.out = (cplx<T>*)out;
+    a.img_stride = (long long)d.Nx * d.Ny;
+    a.nlines = q.col ? d.Ny : d.Nx;
+    a.load_remap = q.load_remap;
+    a.store_remap = q.store_remap;
+    a.line_centered = q.line_centered;
+    a.sign1 = q.sign[0];
+    a.pre = to_arg(q.pre);
+    a.pre.on = q.pre_on && q.pre.nonzero;
+    a.mid_on = q.mid_on;
+    a.mid = to_arg(q.mid);
+    a.scale = (T)q.scale_mid;
+    a.has_t2 = q.ndft >= 2;
+    a.sign2 = q.sign[1];
+    a.post_on = q.post_on;
+    a.post = to_arg(q.post);
+    a.scale2 = (T)q.scale_post;
+    a.sign3 = q.sign[2];
+    return a;
+}
+
+template <typename T>
+hipError_t launch_program_pass(const PlanData& d, int dir, int k, int count, const void* in, void* out,
+                               hipStream_t s) {
+    const ProgPass& q = d.prog[dir].p[k];
+    const PassArgs<T> a = program_args<T>(d, dir, k, in, out);
+    if (q.ndft == 3)
+        return q.col ? launch_n<T, true, true>(d.Nx, a, count, s) : launch_n<T, false, true>(d.Ny, a, count, s);
+    return q.col ? launch_n<T, true>(d.Nx, a, count, s) : launch_n<T, false>(d.Ny, a, count, s);
+}
+
 hipError_t launch_pass(const PlanData& d, int dir, int pass, int count, const void* in, void* out,
                        hipStream_t s) {
+    if (plan_passes(d) != 5)
+        return d.precision == NSLCT_C128 ? launch_program_pass<double>(d, dir, pass, count, in, out, s)
+                                         : launch_program_pass<float>(d, dir, pass, count, in, out, s);
     if (d.precision == NSLCT_C64_SPLIT_F16 || d.precision == NSLCT_C64_SPLIT_BF16) {
         const PassArgs<float> a = pass_args<float>(d, dir, pass, in, out);
         const bool col = (pass == 1 || pass == 3);
@@ -772,7 +855,8 @@ int run_chain(nslct_plan_t plan, int dir, int count, const void* in, void* out, 
     rc = ensure_device_ready();
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    for (int pass = 0; pass < 5; ++pass) {
+    const int np = plan_passes(plan->d);
+    for (int pass = 0; pass < np; ++pass) {
         hipError_t e = launch_pass(plan->d, dir, pass, count, pass == 0 ? in : out, out, s);
         if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("pass launch: ") + hipGetErrorString(e));
     }
@@ -1012,7 +1096,8 @@ int nslct_launch_pass(nslct_plan_t plan, int direction, int pass, int count, con
                       void* stream) {
     if (!plan) return fail(NSLCT_E_ARG, "null plan");
     if (direction != 0 && direction != 1) return fail(NSLCT_E_ARG, "direction must be 0 or 1");
-    if (pass < 0 || pass > 4) return fail(NSLCT_E_ARG, "pass must be in [0, 4]");
+    if (pass < 0 || pass >= plan_passes(plan->d))
+        return fail(NSLCT_E_ARG, "pass must be in [0, nslct_plan_passes)");
     if (count < 1 || count > 65535) return fail(NSLCT_E_ARG, "count must be in [1, 65535]");
     int rc = check_ptrs(in, out);
     if (rc) return rc;
@@ -1020,6 +1105,12 @@ int nslct_launch_pass(nslct_plan_t plan, int direction, int pass, int count, con
     if (rc) return rc;
     hipError_t e = launch_pass(plan->d, direction, pass, count, in, out, (hipStream_t)stream);
     if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("pass launch: ") + hipGetErrorString(e));
+    return NSLCT_OK;
+}
+
+int nslct_plan_passes(nslct_plan_t plan, int* npasses) {
+    if (!plan || !npasses) return fail(NSLCT_E_ARG, "null argument");
+    *npasses = plan_passes(plan->d);
     return NSLCT_OK;
 }
 

@@ -19,6 +19,14 @@
 //      eq. Bnonsym12; type 2: H1, Q1 = (D-I)B1'^-1, B1', Q3 = B1'^-1(A1'-I),
 //      eq. CCCMCCCM16), symmetrised, then the five-slot chain and its adjoint
 //      (eq. CCCMCCCM30) with phase coefficients in fixed-point turns.
+// Reduced decompositions on request (type_override 3..6):
+//   * CM-CC-CM when B is symmetric and invertible (Sec. 4.1, eqs. Bsym04-12):
+//     P1 = (D - I) B^-1, B, P3 = B^-1 (A - I).
+//   * LC-NsDLCT (Sec. 4.2.2, eqs. LC04-LC12): the type-1 form with the
+//     rank-one gauge H = (h, 0; 0, 0), h = (b21 - b12) / a21 (eq. LC08), or
+//     H = (0, 0; 0, h), h = (b12 - b21) / a12 (eq. LC10); with both available,
+//     the smaller eq. HA24 objective.
+//   Both are five-slot chains with zero slots, run as three passes.
 #include "planner.hpp"
 
 #include <algorithm>
@@ -451,6 +459,105 @@ bool supported_size(int n) {
     return false;
 }
 
+ProgPass prog_pass(int col, int lr, int sr, int lcn, int ndft, int s0, int s1, int s2) {
+    ProgPass q{};
+    q.col = col;
+    q.load_remap = lr;
+    q.store_remap = sr;
+    q.line_centered = lcn;
+    q.ndft = ndft;
+    q.sign[0] = s0;
+    q.sign[1] = s1;
+    q.sign[2] = s2;
+    q.scale_mid = q.scale_post = 1.0;
+    return q;
+}
+
+// Three-pass schedules of the reduced chains (rightmost factor first).
+// CM-CC-CM, slots (S0, C1, S4):
+//   rows   [CM(S0)] F_y
+//   cols   F_x CM_w(C1) / Nx F_x^-1          (x centred in, centred out)
+//   rows   F_y^-1 CM(S4) / Ny
+// LC along y (H = (0,0;0,h)):  CM(P1) U^H CM_w(-B') U CM(P3) U_y^H CM_wy(-h) U_y
+//   rows   F_y CM_wy(-h) / Ny F_y^-1 CM(P3) F_y
+//   cols   F_x CM_w(-B') / Nx F_x^-1
+//   rows   F_y^-1 CM(P1) / Ny
+// LC along x swaps the roles of rows and columns.  The inverse (adjoint) runs
+// the reversed factors with negated matrices.
+void fill_program(PlanData* p) {
+    const nslct_stages& s = p->st;
+    const double iNx = 1.0 / p->Nx, iNy = 1.0 / p->Ny;
+    auto turns = [&](const double* m, double sign, bool freq) {
+        double x[3] = {sign * m[0], sign * m[1], sign * m[2]};
+        return make_turns(x, freq ? s.dwx : s.dx, freq ? s.dwy : s.dy);
+    };
+    for (int d = 0; d < 2; ++d) {
+        Program& g = p->prog[d];
+        g.npass = 0;
+        const double sg = d == 0 ? 1.0 : -1.0;  // the inverse negates every matrix
+        if (s.type == 3) {  // mats {P1, B, P3}
+            const double* first = d == 0 ? s.mats[2] : s.mats[0];
+            const double* last = d == 0 ? s.mats[0] : s.mats[2];
+            ProgPass a = prog_pass(0, 1, 0, 1, 1, -1, 0, 0);
+            a.pre = turns(first, sg, false);
+            a.pre_on = a.pre.nonzero;
+            ProgPass b = prog_pass(1, 1, 1, 0, 2, -1, +1, 0);
+            b.mid = turns(s.mats[1], -sg, true);
+            b.mid_on = 1;
+            b.scale_mid = iNx;
+            ProgPass c = prog_pass(0, 0, 1, 1, 1, +1, 0, 0);
+            c.mid = turns(last, sg, false);
+            c.mid_on = 1;
+            c.scale_mid = iNy;
+            g.p[0] = a;
+            g.p[1] = b;
+            g.p[2] = c;
+            g.npass = 3;
+        } else if (s.type == 4 || s.type == 5) {  // mats {P1, B', P3, H}
+            const int lc = s.type == 4 ? 1 : 0;  // LC line axis: x lines are columns
+            const double iNl = lc ? iNx : iNy, iNo = lc ? iNy : iNx;
+            if (d == 0) {
+                ProgPass a = prog_pass(lc, 1, 0, 1, 3, -1, +1, -1);
+                a.mid = turns(s.mats[3], -1.0, true);
+                a.mid_on = 1;
+                a.scale_mid = iNl;
+                a.post = turns(s.mats[2], 1.0, false);
+                a.post_on = a.post.nonzero;
+                ProgPass b = prog_pass(1 - lc, 1, 1, 0, 2, -1, +1, 0);
+                b.mid = turns(s.mats[1], -1.0, true);
+                b.mid_on = 1;
+                b.scale_mid = iNo;
+                ProgPass c = prog_pass(lc, 0, 1, 1, 1, +1, 0, 0);
+                c.mid = turns(s.mats[0], 1.0, false);
+                c.mid_on = 1;
+                c.scale_mid = iNl;
+                g.p[0] = a;
+                g.p[1] = b;
+                g.p[2] = c;
+            } else {
+                ProgPass a = prog_pass(lc, 1, 0, 1, 1, -1, 0, 0);
+                a.pre = turns(s.mats[0], -1.0, false);
+                a.pre_on = a.pre.nonzero;
+                ProgPass b = prog_pass(1 - lc, 1, 1, 0, 2, -1, +1, 0);
+                b.mid = turns(s.mats[1], 1.0, true);
+                b.mid_on = 1;
+                b.scale_mid = iNo;
+                ProgPass c = prog_pass(lc, 0, 1, 1, 3, +1, -1, +1);
+                c.mid = turns(s.mats[2], -1.0, false);
+                c.mid_on = 1;
+                c.scale_mid = iNl;
+                c.post = turns(s.mats[3], 1.0, true);
+                c.post_on = 1;
+                c.scale_post = iNl;
+                g.p[0] = a;
+                g.p[1] = b;
+                g.p[2] = c;
+            }
+            g.npass = 3;
+        }
+    }
+}
+
 void fill_chains(PlanData* p) {
     const nslct_stages& s = p->st;
     double S[5][3] = {};
@@ -458,7 +565,7 @@ void fill_chains(PlanData* p) {
         for (int k = 0; k < 3; ++k) S[slot][k] = sign * x[k];
     };
     // Generic form CM(S0) U CM_w(C1) U^H CM(S2) U CM_w(C3) U^H CM(S4), rightmost first.
-    if (s.type == 1) {  // CM(P1) CC(B') CM(P3) CC(H), CC(X) = F^-1 CM(-X) F
+    if (s.type == 1 || s.type == 4 || s.type == 5) {  // CM(P1) CC(B') CM(P3) CC(H), CC(X) = F^-1 CM(-X) F
         put(1, s.mats[3], -1.0);
         put(2, s.mats[2], 1.0);
         put(3, s.mats[1], -1.0);
@@ -468,6 +575,10 @@ void fill_chains(PlanData* p) {
         put(1, s.mats[2], -1.0);
         put(2, s.mats[1], 1.0);
         put(3, s.mats[0], -1.0);
+    } else if (s.type == 3) {  // CM(P1) CC(B) CM(P3), overall constant +1
+        put(0, s.mats[2], 1.0);
+        put(1, s.mats[1], -1.0);
+        put(4, s.mats[0], 1.0);
     } else {  // CM(C)
         put(0, s.mats[0], 1.0);
     }
@@ -481,6 +592,7 @@ void fill_chains(PlanData* p) {
             p->dir[d].turns[k] = make_turns(p->dir[d].slot[k], freq ? s.dwx : s.dx, freq ? s.dwy : s.dy);
         }
     }
+    fill_program(p);
 }
 
 int check_common(int Nx, int Ny, double dx, double dy, const nslct_opts& o, std::string* err) {
@@ -500,8 +612,8 @@ int check_common(int Nx, int Ny, double dx, double dy, const nslct_opts& o, std:
         *err = "split-precision sides must be 256 or 4096";
         return NSLCT_E_SIZE;
     }
-    if (o.type_override < 0 || o.type_override > 2) {
-        *err = "type_override must be 0, 1 or 2";
+    if (o.type_override < 0 || o.type_override > 6) {
+        *err = "type_override must be in 0..6";
         return NSLCT_E_ARG;
     }
     return NSLCT_OK;
@@ -556,9 +668,61 @@ int build_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, cons
         *err = "B = 0 with A or D != I is an affine map, not decomposable into CMs and CCs";
         return NSLCT_E_NO_DECOMPOSITION;
     }
+    const double dmin = 1e-6 * std::max(1.0, bmax * bmax);
+    if (o.type_override == 3) {  // CM-CC-CM (eq. Bsym08: B symmetric, invertible)
+        if (std::fabs(b.B.a12 - b.B.a21) > 1e-9 * std::max(1.0, bmax)) {
+            *err = "CM-CC-CM needs a symmetric B (eq. Bsym08)";
+            return NSLCT_E_NO_DECOMPOSITION;
+        }
+        const double dt = det(b.B);
+        if (!(std::fabs(dt) >= dmin)) {
+            *err = "CM-CC-CM needs an invertible B (eq. Bsym08)";
+            return NSLCT_E_NO_DECOMPOSITION;
+        }
+        const M2 Bi{b.B.a22 / dt, -b.B.a12 / dt, -b.B.a21 / dt, b.B.a11 / dt};
+        s.type = 3;
+        sym3(mul(minus_eye(b.D), Bi), s.mats[0]);
+        sym3(b.B, s.mats[1]);
+        sym3(mul(Bi, minus_eye(b.A)), s.mats[2]);
+        s.gauge_objective = gamma_ratio(s.mats[0]) * gamma_ratio(s.mats[1]) * gamma_ratio(s.mats[2]);
+        fill_chains(out);
+        return NSLCT_OK;
+    }
+    if (o.type_override >= 4) {  // LC-NsDLCT: rank-one gauge (eqs. LC04-LC10)
+        Gauge g{b, 1, dmin};
+        double best = INFINITY, bh[3] = {0, 0, 0};
+        int btype = 0;
+        for (int t = 4; t <= 5; ++t) {
+            if (o.type_override != 6 && o.type_override != t) continue;
+            const double a = t == 4 ? b.A.a21 : b.A.a12;
+            if (std::fabs(a) < 1e-12) continue;
+            double h[3] = {0, 0, 0};
+            if (t == 4)
+                h[0] = (b.B.a21 - b.B.a12) / a;  // eq. LC08
+            else
+                h[2] = (b.B.a12 - b.B.a21) / a;  // eq. LC10
+            const double f = g.objective(h);
+            if (f < best) {
+                best = f;
+                btype = t;
+                std::memcpy(bh, h, sizeof bh);
+            }
+        }
+        if (!btype) {
+            *err = "no rank-one gauge with invertible B' (eqs. LC08, LC10)";
+            return NSLCT_E_NO_DECOMPOSITION;
+        }
+        double dt;
+        g.stages(bh, s.mats, &dt);
+        s.type = btype;
+        std::memcpy(s.h, bh, sizeof s.h);
+        s.gauge_objective = best;
+        fill_chains(out);
+        return NSLCT_OK;
+    }
     int type = o.type_override;
     if (type == 0) type = (b.B.a11 + b.B.a22) < 0 ? 2 : 1;
-    Gauge g{b, type, 1e-6 * std::max(1.0, bmax * bmax)};
+    Gauge g{b, type, dmin};
     GaugeOut go = solve(g, mmax);
     if (o.type_override == 0 && !go.feasible) {
         g.type = type = 3 - type;
@@ -581,11 +745,16 @@ int build_plan_from_stages(const nslct_stages& st, int Nx, int Ny, const nslct_o
                            std::string* err) {
     int rc = check_common(Nx, Ny, st.dx, st.dy, o, err);
     if (rc) return rc;
-    if (st.type < 0 || st.type > 2) {
-        *err = "stage type must be 0, 1 or 2";
+    if (st.type < 0 || st.type > 5) {
+        *err = "stage type must be in 0..5";
         return NSLCT_E_ARG;
     }
-    const int nm = st.type == 0 ? 1 : 4;
+    const int nm = st.type == 0 ? 1 : st.type == 3 ? 3 : 4;
+    if ((st.type == 4 && (st.mats[3][1] != 0 || st.mats[3][2] != 0)) ||
+        (st.type == 5 && (st.mats[3][0] != 0 || st.mats[3][1] != 0))) {
+        *err = "LC stages need H = (h, 0; 0, 0) (type 4) or (0, 0; 0, h) (type 5)";
+        return NSLCT_E_ARG;
+    }
     for (int i = 0; i < nm; ++i)
         for (int k = 0; k < 3; ++k)
             if (!std::isfinite(st.mats[i][k])) {
@@ -600,6 +769,8 @@ int build_plan_from_stages(const nslct_stages& st, int Nx, int Ny, const nslct_o
     s.type = st.type;
     for (int i = 0; i < nm; ++i)
         for (int k = 0; k < 3; ++k) s.mats[i][k] = st.mats[i][k];
+    if (st.type >= 4)
+        for (int k = 0; k < 3; ++k) s.h[k] = st.mats[3][k];
     s.dx = st.dx;
     s.dy = st.dy;
     s.dwx = kTwoPi / (Nx * st.dx);
@@ -726,7 +897,7 @@ void stage_gradient(const PlanData& p, const double sums[15], double g[12]) {
         for (int k = 0; k < 3; ++k) g[3 * m + k] = sg * slot[j][k];
     };
     for (int k = 0; k < 12; ++k) g[k] = 0;
-    if (p.st.type == 1) {  // {P1, B', P3, H} = {S4, -C3, S2, -C1}
+    if (p.st.type == 1 || p.st.type == 4 || p.st.type == 5) {  // {P1, B', P3, H} = {S4, -C3, S2, -C1}
         put(0, 4, 1.0);
         put(1, 3, -1.0);
         put(2, 2, 1.0);
@@ -736,6 +907,10 @@ void stage_gradient(const PlanData& p, const double sums[15], double g[12]) {
         put(1, 2, 1.0);
         put(2, 1, -1.0);
         put(3, 0, 1.0);
+    } else if (p.st.type == 3) {  // {P1, B, P3} = {S4, -C1, S0}
+        put(0, 4, 1.0);
+        put(1, 1, -1.0);
+        put(2, 0, 1.0);
     } else {
         put(0, 0, 1.0);
     }

@@ -26,11 +26,32 @@ struct Chain5 {
     ChirpTurns turns[5];
 };
 
+// One pass of a reduced schedule: a line pass over rows (y lines) or
+// columns (x lines) doing [pre] DFT [mid] [DFT] [post] [DFT] in registers.
+struct ProgPass {
+    int col;            // 0: rows (y lines, contiguous), 1: columns (x lines)
+    int load_remap;     // centred -> FFT order along the line at load
+    int store_remap;    // FFT -> centred order along the line at store
+    int line_centered;  // the line index is stored in centred order
+    int ndft;           // 1..3 line DFTs
+    int sign[3];        // exponent signs of the DFTs
+    int pre_on, mid_on, post_on;  // pointwise products (chirp and/or scale)
+    double scale_mid, scale_post;
+    ChirpTurns pre, mid, post;
+};
+
+// Reduced schedule of the CM-CC-CM and LC chains: three passes.
+struct Program {
+    int npass;  // 0: the five-pass chain of Chain5 is used
+    ProgPass p[5];
+};
+
 struct PlanData {
     nslct_stages st;
     int Nx, Ny;
     int precision;
-    Chain5 dir[2];  // [0] forward, [1] inverse (adjoint)
+    Chain5 dir[2];     // [0] forward, [1] inverse (adjoint): five-slot form
+    Program prog[2];   // reduced three-pass schedule of the same chain
 };
 
 // Symmetric 2x2 (x11, x12, x22) helpers exposed for tests of the planner.

@@ -180,3 +180,62 @@ def test_lie_point_and_plan_jacobian_against_oracle(nl):
             for k, (a, b) in enumerate([(0, 0), (0, 1), (1, 1)]):
                 ref[3 * m + k, i] = (pp.mats[m][a, b] - pm.mats[m][a, b]) / (2 * h)
     assert np.max(np.abs(jac - ref)) <= 1e-6 * max(1.0, np.max(np.abs(ref)))
+
+
+def _sym_matrices_cmccm(seed, count):
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        X = [rng.normal(size=(2, 2)) * s for s in (0.5, 1.0, 0.5)]
+        P1, B, P3 = [0.5 * (x + x.T) for x in X]
+        if abs(np.linalg.det(B)) > 0.05:
+            out.append(_cm4(P1) @ _cc4(B) @ _cm4(P3))
+    return out
+
+
+def test_reduced_types_match_oracle_stages(nl):
+    """type_override 3 (CM-CC-CM, eq. Bsym04) and 4 / 5 / 6 (LC-NsDLCT, eqs.
+    LC08 / LC10, objective choice) give the oracle's stage matrices; the
+    single-image path then has three passes."""
+    from oracle import fast
+    for M in _sym_matrices_cmccm(3, 4):
+        p = nl.Plan(M, 32, 32, 0.5, 0.5, type_override=3)
+        st = p.stages()
+        ref = fast.cmccm_plan(M, 32, 32, 0.5, 0.5)
+        assert st["type"] == 3 and p.passes() == 3
+        for a, b in zip(st["mats"][:3], ref.mats):
+            assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.max(np.abs(b)))
+        assert not np.any(st["mats"][3])
+    c = synth.symplectic_candidates(11)
+    for _ in range(6):
+        M = next(c)
+        for override, axis in ((4, 0), (5, 1), (6, None)):
+            try:
+                ref = fast.lc_plan(M, 32, 32, 0.5, 0.5, axis=axis)
+            except fast.NotApplicable:
+                assert _cplan(nl, M, 32, 32, 0.5, 0.5, opts=_opts(nl, override)) == -3
+                continue
+            p = nl.Plan(M, 32, 32, 0.5, 0.5, type_override=override)
+            st = p.stages()
+            assert st["type"] == 4 + ref.axis and p.passes() == 3
+            for a, b in zip(st["mats"], ref.mats):
+                assert np.max(np.abs(a - b)) <= 1e-10 * max(1.0, np.max(np.abs(b)))
+            assert st["f"] == pytest.approx(ref.f, rel=1e-12)
+    # Not applicable: CM-CC-CM with a non-symmetric B, LC for the FT (A = 0).
+    assert _cplan(nl, next(synth.symplectic_candidates(7)), opts=_opts(nl, 3)) == -3
+    FT = np.block([[np.zeros((2, 2)), np.eye(2)], [-np.eye(2), np.zeros((2, 2))]])
+    assert _cplan(nl, FT, opts=_opts(nl, 6)) == -3
+    # The five-pass paths report five passes; reduced stages round-trip.
+    assert nl.Plan(FT, 16, 16).passes() == 5
+    st = nl.Plan(FT, 16, 16, type_override=3).stages()
+    q = nl.Plan.from_stages(3, st["mats"], 16, 16, 1.0, 1.0)
+    assert q.passes() == 3 and q.stages()["type"] == 3
+    bad = [np.eye(2), np.eye(2), np.eye(2), np.array([[1.0, 0.5], [0.5, 0.0]])]
+    with pytest.raises(nl.NslctError):
+        nl.Plan.from_stages(4, bad, 16, 16, 1.0, 1.0)
+
+
+def _opts(nl, override):
+    o = nl.lib.opts()
+    o.type_override = override
+    return o

@@ -1,0 +1,131 @@
+"""GPU parity of the reduced three-pass schedules: CM-CC-CM (type 3, Sec.
+4.1, eq. Bsym12) and LC-NsDLCT (types 4 / 5, Sec. 4.2.2, eq. LC12), against
+the FP64 oracle (``oracle.fast``) and against the five-pass execution of the
+same stage matrices (an LC chain is a type-1 chain whose gauge has rank one).
+
+Bars (relative L2): complex128 <= 1e-11, complex64 <= 1e-5 against the
+oracle; three-pass vs five-pass of the same stages <= 1e-12 (complex128);
+launch_pass chain == forward bitwise.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import chain, fast
+
+pytestmark = pytest.mark.gpu
+I2, Z2 = np.eye(2), np.zeros((2, 2))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def nl(torch):
+    import paper_1707_03688_amd as _nl
+    return _nl
+
+
+def _cmccm_matrix(seed):
+    rng = np.random.default_rng(seed)
+    while True:
+        P1, B, P3 = [0.5 * (x + x.T) for x in (rng.normal(size=(2, 2)) * s for s in (0.5, 1.0, 0.5))]
+        if abs(np.linalg.det(B)) > 0.05:
+            return (np.block([[I2, Z2], [P1, I2]]) @ np.block([[I2, B], [Z2, I2]])
+                    @ np.block([[I2, Z2], [P3, I2]]))
+
+
+def _lc_matrix(seed):
+    c = synth.symplectic_candidates(seed)
+    while True:
+        M = next(c)
+        if fast.lc_candidates(M):
+            return M
+
+
+SHAPES = [(64, 64), (32, 128), (128, 48), (96, 256)]
+
+
+def _oracle_plan(typ, M, Nx, Ny, d):
+    if typ == 3:
+        return fast.cmccm_plan(M, Nx, Ny, d, d)
+    return fast.lc_plan(M, Nx, Ny, d, d, axis=typ - 4)
+
+
+@pytest.mark.parametrize("typ", [3, 4, 5])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_three_pass_matches_oracle(torch, nl, typ, shape, precision):
+    Nx, Ny = shape
+    d = math.sqrt(2 * math.pi / max(Nx, Ny))
+    M = _cmccm_matrix(Nx + Ny) if typ == 3 else _lc_matrix(Nx + Ny)
+    p = nl.Plan(M, Nx, Ny, d, d, precision=precision, type_override=typ)
+    assert p.passes() == 3 and p.stages()["type"] == typ
+    po = _oracle_plan(typ, M, Nx, Ny, d)
+    g = synth.complex_normal(shape, seed=Nx * Ny)
+    dt = torch.complex128 if precision == "c128" else torch.complex64
+    x = torch.from_numpy(g).to(dt).cuda()
+    G = p.forward(x)
+    tol = 1e-11 if precision == "c128" else 1e-5
+    assert chain.rel_l2(G.cpu().numpy(), fast.forward(po, g)) <= tol
+    back = p.inverse(G).cpu().numpy()
+    assert chain.rel_l2(back, g) <= tol
+    Gi = synth.complex_normal(shape, seed=7)
+    got = p.inverse(torch.from_numpy(Gi).to(dt).cuda()).cpu().numpy()
+    assert chain.rel_l2(got, fast.inverse(po, Gi)) <= tol
+
+
+@pytest.mark.parametrize("typ", [4, 5])
+def test_lc_three_pass_equals_five_pass_of_same_stages(torch, nl, typ):
+    Nx, Ny = 256, 128
+    d = math.sqrt(2 * math.pi / 256)
+    M = _lc_matrix(3)
+    p3 = nl.Plan(M, Nx, Ny, d, d, precision="c128", type_override=typ)
+    st = p3.stages()
+    p5 = nl.Plan.from_stages(1, st["mats"], Nx, Ny, d, d, "c128")
+    assert p5.passes() == 5
+    x = torch.from_numpy(synth.complex_normal((Nx, Ny), seed=5)).cuda()
+    a, b = p3.forward(x), p5.forward(x)
+    assert (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item() <= 1e-12
+    a, b = p3.inverse(x), p5.inverse(x)
+    assert (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item() <= 1e-12
+
+
+@pytest.mark.parametrize("typ", [3, 5])
+def test_passes_many_and_inplace_are_bitwise(torch, nl, typ):
+    N = 1024
+    d = math.sqrt(2 * math.pi / N)
+    M = _cmccm_matrix(1) if typ == 3 else _lc_matrix(1)
+    p = nl.Plan(M, N, N, d, d, type_override=typ)
+    x = torch.from_numpy(synth.complex_normal((3, N, N), seed=2)).to(torch.complex64).cuda()
+    ref = p.forward(x)
+    y = torch.empty_like(x[0])
+    for k in range(p.passes()):
+        p.launch_pass(0, k, x[1] if k == 0 else y, y)
+    assert torch.equal(y, ref[1])
+    z = x[2].clone()
+    p.forward(z, out=z)
+    assert torch.equal(z, ref[2])
+    with pytest.raises(nl.NslctError):
+        p.launch_pass(0, 3, y, y)
+
+
+@pytest.mark.parametrize("typ", [3, 5])
+def test_1024_against_oracle(torch, nl, typ):
+    """The headline size, complex64, against the FP64 oracle (relative L2 <= 1e-5)."""
+    N = 1024
+    d = math.sqrt(2 * math.pi / N)
+    M = _cmccm_matrix(11) if typ == 3 else _lc_matrix(11)
+    p = nl.Plan(M, N, N, d, d, type_override=typ)
+    g = synth.complex_normal((N, N), seed=1)
+    G = p.forward(torch.from_numpy(g).to(torch.complex64).cuda()).cpu().numpy()
+    assert chain.rel_l2(G, fast.forward(_oracle_plan(typ, M, N, N, d), g)) <= 1e-5
