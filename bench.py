@@ -69,6 +69,42 @@ def cpu_baseline(M_plan_stages, g, budget_s: float = 20.0):
     return runs / t_total, threads, runs, out
 
 
+def cpu_fft_chain(st, g, N, d, budget_s: float = 10.0):
+    """Same-algorithm CPU baseline: the unitary five-slot chain of the plan's
+    stage matrices with pocketfft (scipy.fft, complex128, all host threads)."""
+    import numpy as np
+    import scipy.fft as sf
+    typ, P = st["type"], st["mats"]
+    Z = np.zeros((2, 2))
+    slots = {1: [Z, -P[3], P[2], -P[1], P[0]], 2: [P[3], -P[2], P[1], -P[0], Z]}[typ]
+    m = np.arange(N) - N // 2
+    dw = 2 * np.pi / (N * d)
+
+    def cm(x, S, du):
+        ph = 0.5 * S[0, 0] * du * du * (m[:, None] ** 2) + S[0, 1] * du * du * np.outer(m, m) \
+            + 0.5 * S[1, 1] * du * du * (m[None, :] ** 2)
+        return x * np.exp(1j * ph)
+
+    def U(x, inv):
+        f = sf.ifft2 if inv else sf.fft2
+        return sf.fftshift(f(sf.ifftshift(x), norm="ortho", workers=-1))
+
+    def run():
+        x = cm(g.astype(np.complex128), slots[0], d)
+        x = U(cm(U(x, False), slots[1], dw), True)
+        x = cm(x, slots[2], d)
+        x = U(cm(U(x, False), slots[3], dw), True)
+        return cm(x, slots[4], d)
+
+    runs, t_total, out = 0, 0.0, None
+    while runs < 1 or (t_total < budget_s and runs < 20):
+        t0 = time.perf_counter()
+        out = run()
+        t_total += time.perf_counter() - t0
+        runs += 1
+    return runs / t_total, runs, out
+
+
 def bench_batched(nl, torch, synth, np, count=256, seed=2):
     """Ragged batch: `count` images, sides uniform over 128..1024 (two of them
     3 * 2^k), each with its own seeded symplectic ABCD; one graph replay per
@@ -157,6 +193,32 @@ def bench_split(nl, torch, synth, np, count=8, N=4096, reps=3):
     return res
 
 
+def bench_reduced(nl, torch, M, N, d, ins, outs, K):
+    """Three-pass schedules at the headline size: LC-NsDLCT (rank-one gauge,
+    orientation by the eq. HA24 objective) of the headline matrix, and
+    CM-CC-CM of a gyrator (symmetric B).  48 B per sample per transform."""
+    import numpy as np
+    R = len(ins)
+    phi = 0.7
+    S = np.array([[0.0, 1.0], [1.0, 0.0]])
+    gyr = np.block([[np.cos(phi) * np.eye(2), np.sin(phi) * S], [-np.sin(phi) * S, np.cos(phi) * np.eye(2)]])
+    out = {}
+    for name, MM, typ in (("lc_headline_matrix", M, 6), ("cmccm_gyrator_0.7", gyr, 3)):
+        p = nl.Plan(MM, N, N, d, d, type_override=typ)
+        for i in range(5):
+            p.forward(ins[i % R], out=outs[i % R])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(K):
+            p.forward(ins[i % R], out=outs[i % R])
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / K
+        out[name] = {"stage_type": p.stages()["type"], "passes": p.passes(), "us_per_transform": sec * 1e6,
+                     "NsLCT_per_s": 1 / sec, "hbm_effective_GBps": 48.0 * N * N / sec / 1e9,
+                     "pct_hbm_peak": 48.0 * N * N / sec / 1e9 / HBM_PEAK_GBPS * 100}
+    return out
+
+
 def bench_backward(nl, torch, synth, np, count=32, N=512, reps=10):
     """One training step of loss = ||NsDLCT_M(theta)(x) - y||^2 on `count`
     images of N x N (y: the transform under a perturbed matrix): forward,
@@ -220,6 +282,7 @@ def main():
     ap.add_argument("--split", type=int, default=1, help="also time the split-precision 8 x 4096^2 leg")
     ap.add_argument("--conc", type=int, default=1, help="also time 8 transforms per launch")
     ap.add_argument("--backward", type=int, default=1, help="also time the 32 x 512^2 fwd+bwd step")
+    ap.add_argument("--reduced", type=int, default=1, help="also time the three-pass LC / CM-CC-CM schedules")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched and "
@@ -315,12 +378,30 @@ def main():
         conc = 8 * reps / (c0.elapsed_time(c1) * 1e-3)
         del x8, y8
 
+    reduced = bench_reduced(nl, torch, M, N, d, ins, outs, K) if args.reduced else None
     batched = bench_batched(nl, torch, synth, np) if args.batched else None
     split = bench_split(nl, torch, synth, np) if args.split else None
     bwd = bench_backward(nl, torch, synth, np) if args.backward else None
 
     plan.forward(ins[0], out=outs[0])
     G = outs[0].cpu().numpy()
+    back = plan.inverse(outs[0])
+    recon = (torch.linalg.vector_norm(back - ins[0]) / torch.linalg.vector_norm(ins[0])).item()
+
+    # The small case: one 64 x 64 complex128 image per call (latency-bound).
+    N0 = 64
+    _, M0, _ = draw_matrix(0, N0, 1.0, nl)
+    p0 = nl.Plan(M0, N0, N0, 1.0, 1.0, precision="c128")
+    x0s = torch.from_numpy(synth.complex_normal((N0, N0), seed=0)).cuda()
+    y0s = torch.empty_like(x0s)
+    for _ in range(10):
+        p0.forward(x0s, out=y0s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        p0.forward(x0s, out=y0s)
+    torch.cuda.synchronize()
+    c0_us = (time.perf_counter() - t0) / K * 1e6
     result = {
         "metric": METRIC,
         "value": value,
@@ -346,11 +427,16 @@ def main():
         "hbm_effective_GBps": 80.0 * px * value / 1e9,
         "pct_hbm_peak": 80.0 * px * value / 1e9 / HBM_PEAK_GBPS * 100,
         "copy_kernel_GBps": copy_gbps,
+        "forward_inverse_rel_l2": recon,
+        "small_64_c128": {"us_per_transform": c0_us, "NsLCT_per_s": 1e6 / c0_us,
+                          "note": "64 x 64 complex128, unit spacing, one image per call"},
     }
     if conc:
         result["concurrent8"] = {"value": conc, "unit": "NsLCT/s",
                                  "pct_hbm_peak": 80.0 * px * conc / 1e9 / HBM_PEAK_GBPS * 100,
                                  "note": "8 independent 1024x1024 transforms per launch (grid.y = 8)"}
+    if reduced:
+        result["reduced_schedules_1024"] = reduced
     if batched:
         result["batched_ragged"] = batched
     if split:
@@ -364,6 +450,10 @@ def main():
                                   "sample": f"{runs} forward transform(s) of the same 1024x1024 image "
                                             "by the FP64 dense-DFT oracle chain"}
         result["rel_l2_vs_fp64_oracle"] = chain.rel_l2(G, ref)
+        frate, fruns, fout = cpu_fft_chain(st, g, N, d)
+        result["cpu_fft_chain"] = {"value": frate, "unit": "NsLCT/s", "threads": os.cpu_count(),
+                                   "sample": f"{fruns} forward transform(s), scipy.fft complex128",
+                                   "rel_l2_gpu_vs_it": float(np.linalg.norm(G - fout) / np.linalg.norm(fout))}
     print(json.dumps(result), flush=True)
 
 

@@ -171,9 +171,10 @@ __device__ __forceinline__ int store_to_fft(int p) {
 
 // One fused pass over LINES lines of length N per workgroup.  Row passes
 // (COL = false) read and write contiguous lines directly.  Column passes
-// stage a tile of LINES adjacent columns through LDS: the global accesses
-// then cover LINES consecutive samples of each row (coalesced), while each
-// line's FFT work stays with the TPL threads that own it.
+// cover a tile of LINES adjacent columns; their stores (and, for lines
+// longer than a wavefront, their loads) are staged through LDS so that the
+// global accesses cover LINES consecutive samples of each row (coalesced),
+// while each line's FFT work stays with the TPL threads that own it.
 template <typename T, int N, bool COL, int LINES, int NS = 1, bool X3 = false>
 __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t img_off, cplx<T>* lds_all) {
     constexpr int TPL = LinePlan<N>::TPL;
@@ -205,7 +206,20 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
 #pragma unroll
     for (int sg = 0; sg < NS; ++sg) {
         const cplx<T>* __restrict__ in = ins[sg];
-        if constexpr (COL) {
+        if constexpr (COL && F::kWave) {
+            // Lines owned by one wavefront: each lane loads its own column
+            // samples directly.  The tile's other columns are read by the
+            // neighbouring wavefronts of the workgroup at the same time, so
+            // the 32-byte row segments are still served by one cache line,
+            // and no workgroup barrier couples the wavefronts before their
+            // FFTs (measured faster than staging through LDS at N <= 1024).
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int p = pos(r);
+                const int src = a.load_remap ? fft_to_store<N>(p) : p;
+                v[sg][r] = active ? in[(size_t)src * nl + line] : cplx<T>{0, 0};
+            }
+        } else if constexpr (COL) {
             // Coalesced tile load: lane -> (column c, row group u).
             const int c = tid % LINES;
             const int u = tid / LINES;

@@ -56,7 +56,7 @@ def _pair(nl, M, Nx, Ny, dx, dy, typ=None, precision="c64"):
 
 
 SHAPES = [(64, 64), (128, 32), (16, 256), (8, 8), (2, 4), (4, 2), (32, 512), (1024, 16), (16, 1024),
-          (256, 128), (2048, 8), (8, 4096),
+          (256, 128), (2048, 8), (8, 4096), (4096, 16),
           # 3 * 2^k lengths (radix-3 stages), mixed with powers of two
           (384, 384), (768, 64), (48, 96), (6, 12), (24, 192), (128, 768)]
 
