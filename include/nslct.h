@@ -211,10 +211,12 @@ int nslct_plan_stage_gradient(nslct_plan_t plan, const double sums[15], double g
 int nslct_lie_point(const double abcd[16], const double theta[10], double out[16]);
 
 /* Host: d(stage entries)/d(theta) at theta0, jac[12][10] row-major, for
- * M(theta) = M expm(J S(theta)): central differences of the planner (gauge
- * re-solved at every point, decomposition type held) with step h in
- * (0, 1e-2].  Valid where the gauge minimiser moves smoothly (its set of
- * vanishing stage entries does not change within +-h). */
+ * M(theta) = M expm(J S(theta)): central differences of the planner with
+ * step h in (0, 1e-2], decomposition type held; at theta0 +- h the eq. HA24
+ * minimiser is followed from the one at theta0 (local Nelder-Mead and kink
+ * snapping instead of the full grid search).  Valid where the minimiser
+ * moves smoothly (its set of vanishing stage entries does not change within
+ * +-h). */
 int nslct_plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny, double dx, double dy,
                         const nslct_opts* opts, double h, double jac[12 * 10]);
 

@@ -10,7 +10,8 @@ the forward output and on the incoming gradient together (the transform is
 unitary, so dLoss/dx = L^H grad), and collects the derivative with respect to
 every stage-matrix entry at the chirp points; ``nslct_plan_stage_gradient``
 turns those sums into dLoss/d(stage entries) and ``nslct_plan_jacobian``
-gives d(stage entries)/d(theta) (planner re-solved at theta +- h), whose
+gives d(stage entries)/d(theta) (planner at theta +- h, its gauge followed
+from the one at theta), whose
 product is dLoss/dtheta.  The binding only marshals arguments.
 """
 from __future__ import annotations

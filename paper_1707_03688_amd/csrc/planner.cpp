@@ -243,7 +243,12 @@ double nelder_mead(Fn& f, double* s, int dim, double size) {
 }
 
 // Exhaustive HA gauge search (eq. HA24).
-GaugeOut solve(const Gauge& g, double mmax) {
+// Gauge search of eq. HA24.  With `start` == nullptr: exhaustive grid over
+// the feasible set, then Nelder-Mead from the best distinct cells.  With a
+// start gauge (a neighbouring optimum, used by the Jacobian's difference
+// quotients): Nelder-Mead from its projection onto this feasible set only.
+// Kink snapping follows in both cases.
+GaugeOut solve(const Gauge& g, double mmax, const double* start = nullptr) {
     GaugeOut out;
     double c[3], rhs;
     g.equation(c, &rhs);
@@ -291,11 +296,20 @@ GaugeOut solve(const Gauge& g, double mmax) {
 
     const double R = 4.0 * (1.0 + mmax);
     const int G = dim == 2 ? 513 : 81;
-    const double step = 2.0 * R / (G - 1);
+    double step = 2.0 * R / (G - 1);
+    std::vector<std::array<double, 3>> starts;
+    if (start) {
+        // Coordinates of the start gauge's projection onto the feasible set.
+        std::array<double, 3> s0{0, 0, 0};
+        for (int k = 0; k < dim; ++k)
+            for (int i = 0; i < 3; ++i) s0[k] += U[i][k] * (start[i] - h0[i]);
+        starts.push_back(s0);
+        step = 1e-3 * (1.0 + std::fabs(s0[0]) + std::fabs(s0[1]) + std::fabs(s0[2]));
+    }
     // Grid evaluation.
     std::vector<std::pair<double, std::array<int, 3>>> cells;
-    cells.reserve(dim == 2 ? G * G : G * G * G);
-    {
+    if (!start) cells.reserve(dim == 2 ? G * G : G * G * G);
+    if (!start) {
         double s[3] = {0, 0, 0};
         const int G3 = dim == 3 ? G : 1;
         for (int i = 0; i < G; ++i)
@@ -308,24 +322,27 @@ GaugeOut solve(const Gauge& g, double mmax) {
                     if (std::isfinite(f)) cells.push_back({f, {i, j, k}});
                 }
     }
-    if (cells.empty()) return out;
-    std::sort(cells.begin(), cells.end(),
-              [](const auto& x, const auto& y) { return x.first < y.first; });
-    std::vector<std::array<int, 3>> seeds;
-    for (const auto& cell : cells) {
-        bool far = true;
-        for (const auto& s : seeds) {
-            int dmax = 0;
-            for (int k = 0; k < dim; ++k) dmax = std::max(dmax, std::abs(cell.second[k] - s[k]));
-            if (dmax <= 3) far = false;
+    if (!start) {
+        if (cells.empty()) return out;
+        std::sort(cells.begin(), cells.end(),
+                  [](const auto& x, const auto& y) { return x.first < y.first; });
+        std::vector<std::array<int, 3>> seeds;
+        for (const auto& cell : cells) {
+            bool far = true;
+            for (const auto& sd : seeds) {
+                int dmax = 0;
+                for (int k = 0; k < dim; ++k) dmax = std::max(dmax, std::abs(cell.second[k] - sd[k]));
+                if (dmax <= 3) far = false;
+            }
+            if (far) seeds.push_back(cell.second);
+            if (seeds.size() >= 16) break;
         }
-        if (far) seeds.push_back(cell.second);
-        if (seeds.size() >= 16) break;
+        for (const auto& sd : seeds) starts.push_back({-R + step * sd[0], -R + step * sd[1], -R + step * sd[2]});
     }
 
     std::vector<Cand> cands;
-    for (const auto& sd : seeds) {
-        double s[3] = {-R + step * sd[0], -R + step * sd[1], -R + step * sd[2]};
+    for (const auto& st0 : starts) {
+        double s[3] = {st0[0], st0[1], st0[2]};
         if (dim == 2) s[2] = 0;
         double f = nelder_mead(fs, s, dim, step);
         // Restart from the result with a fresh simplex: Nelder-Mead can
@@ -625,8 +642,21 @@ double gamma_ratio(const double x[3]) {
     return (std::fabs(x[0]) + std::fabs(x[1]) + 1.0) * (std::fabs(x[1]) + std::fabs(x[2]) + 1.0);
 }
 
+namespace {
+int build_plan_from(const double abcd[16], int Nx, int Ny, double dx, double dy, const nslct_opts& o,
+                    PlanData* out, std::string* err, const double* start_gauge);
+}  // namespace
+
 int build_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, const nslct_opts& o,
                PlanData* out, std::string* err) {
+    return build_plan_from(abcd, Nx, Ny, dx, dy, o, out, err, nullptr);
+}
+
+namespace {
+// start_gauge: a gauge of a neighbouring matrix to follow locally (HA types
+// with type_override 1 or 2 only), else the full search.
+int build_plan_from(const double abcd[16], int Nx, int Ny, double dx, double dy, const nslct_opts& o,
+                    PlanData* out, std::string* err, const double* start_gauge) {
     int rc = check_common(Nx, Ny, dx, dy, o, err);
     if (rc) return rc;
     for (int i = 0; i < 16; ++i)
@@ -723,7 +753,9 @@ int build_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, cons
     int type = o.type_override;
     if (type == 0) type = (b.B.a11 + b.B.a22) < 0 ? 2 : 1;
     Gauge g{b, type, dmin};
-    GaugeOut go = solve(g, mmax);
+    GaugeOut go;
+    if (start_gauge && o.type_override != 0) go = solve(g, mmax, start_gauge);
+    if (!go.found) go = solve(g, mmax);
     if (o.type_override == 0 && !go.feasible) {
         g.type = type = 3 - type;
         go = solve(g, mmax);
@@ -740,6 +772,8 @@ int build_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, cons
     fill_chains(out);
     return NSLCT_OK;
 }
+
+}  // namespace
 
 int build_plan_from_stages(const nslct_stages& st, int Nx, int Ny, const nslct_opts& o, PlanData* out,
                            std::string* err) {
@@ -865,8 +899,8 @@ int plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny
         lie_point(abcd, tp, Mp);
         lie_point(abcd, tm, Mm);
         PlanData pp, pm;
-        rc = build_plan(Mp, Nx, Ny, dx, dy, of, &pp, err);
-        if (!rc) rc = build_plan(Mm, Nx, Ny, dx, dy, of, &pm, err);
+        rc = build_plan_from(Mp, Nx, Ny, dx, dy, of, &pp, err, base.st.h);
+        if (!rc) rc = build_plan_from(Mm, Nx, Ny, dx, dy, of, &pm, err, base.st.h);
         if (rc) return rc;
         if (pp.st.type != pm.st.type) {
             *err = "decomposition type changes within the difference step";

@@ -100,14 +100,17 @@ def test_config0_c128_against_dense_operator(torch, nl):
         assert chain.rel_l2(G, dense.apply_sequential(po, g)) <= TOL["c128"]
 
 
-def test_config1_1024_c64_and_reconstruction(torch, nl):
-    """1024 x 1024 complex64 with spacing sqrt(2 pi / 1024): full-image parity
+@pytest.mark.parametrize("field", ["normal", "random_phase"])
+def test_config1_1024_c64_and_reconstruction(torch, nl, field):
+    """1024 x 1024 complex64 with spacing sqrt(2 pi / 1024), i.i.d. normal
+    samples or the Gaussian-windowed random-phase field: full-image parity
     with the oracle, and forward -> inverse reconstruction."""
     N = 1024
     d = math.sqrt(2 * math.pi / N)
     M = _draws(1, 1)[0]
     po, pg = _pair(nl, M, N, N, d, d)
-    g = synth.complex_normal((N, N), seed=1)
+    g = (synth.complex_normal((N, N), seed=1) if field == "normal"
+         else synth.random_phase_field(N, d, seed=1))
     x = _to_gpu(torch, g, "c64")
     G = pg.forward(x)
     assert chain.rel_l2(G.cpu().numpy(), chain.forward(po, g)) <= TOL["c64"]
