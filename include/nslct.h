@@ -18,6 +18,10 @@
  *   the minimiser of the phase-space growth product of eq. HA24.
  *   The chain equals a unitary operator L; nslct_inverse applies L^H = L^-1,
  *   the reversed chain with negated stage matrices (eq. CCCMCCCM30).
+ *   On request the reduced decompositions are planned instead: CM-CC-CM for
+ *   a symmetric invertible B (Sec. 4.1, eq. Bsym12) and the low-complexity
+ *   LC-NsDLCT with a rank-one gauge (Sec. 4.2.2, eq. LC12), three passes
+ *   over the image instead of five (see nslct_opts.type_override).
  *
  * Data layout (all entry points)
  *   An image is Nx*Ny interleaved complex numbers (re, im), row-major
@@ -58,7 +62,7 @@ extern "C" {
 #define NSLCT_E_NO_DECOMPOSITION (-3) /* no symmetric gauge with invertible B' */
 #define NSLCT_E_SIZE (-4)             /* unsupported Nx, Ny */
 #define NSLCT_E_HIP (-5)              /* HIP runtime error (message kept) */
-#define NSLCT_E_UNSUPPORTED (-6)      /* valid request this build does not do */
+#define NSLCT_E_UNSUPPORTED (-6)      /* valid request the library does not implement */
 
 /* Precision of storage and arithmetic. */
 #define NSLCT_C64 0  /* complex64 storage, FP32 butterflies, FP64-exact phases */

@@ -97,7 +97,10 @@ class NsLCTFunction(torch.autograd.Function):
         grad_x, sums = backward_sums(plan, G, grad_out.contiguous())
         M0, th, Nx, Ny, dx, dy, precision, typ = ctx.meta
         gst = stage_gradient(plan, sums.cpu().numpy())
-        jac = plan_jacobian(M0, th, Nx, Ny, dx, dy, precision, type_override=typ)
+        # Closed-form stages (types 3-5) take a smaller difference step than
+        # the searched HA gauge, whose minimiser is resolved to ~1e-12.
+        jac = plan_jacobian(M0, th, Nx, Ny, dx, dy, precision, type_override=typ,
+                            h=1e-5 if typ >= 3 else 1e-4)
         gtheta = jac.T @ gst
         dtype, device = ctx.theta_meta
         return grad_x, torch.as_tensor(gtheta, dtype=dtype, device=device), None, None, None, None, None

@@ -385,10 +385,6 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
     }
 }
 
-template <typename T, int N>
-constexpr size_t lds_bytes(int lines) {
-    return (size_t)lines * lds_line_elems<N>() * sizeof(cplx<T>);
-}
 
 // Single-plan pass: blockIdx.x = line tile, blockIdx.y = image.
 template <typename T, int N, bool COL, int LINES, bool X3 = false>
@@ -402,11 +398,18 @@ template <typename T, int N>
 constexpr int row_lines() {
     return LinePlan<N>::TPL >= 256 ? 1 : 256 / LinePlan<N>::TPL;
 }
+// Columns per tile: 4 (complex64) or 2 (complex128) adjacent columns, so a
+// row segment is 32 bytes, but no more than 512 threads per workgroup: a
+// 4096-long complex64 tile of 4 columns (1024 threads, 139 KB of LDS, one
+// workgroup per CU in lock step) measured 1.6x slower than 2 columns (two
+// independent workgroups per CU).
 template <typename T, int N>
 constexpr int col_lines() {
+    constexpr int TPL = LinePlan<N>::TPL;
     constexpr int cmin = sizeof(T) == 4 ? 4 : 2;
-    constexpr int c = 256 / LinePlan<N>::TPL;
-    return c > cmin ? c : cmin;
+    constexpr int cap = 512 / TPL;
+    constexpr int c = cmin < cap ? cmin : cap;
+    return 256 / TPL > c ? 256 / TPL : c;
 }
 
 template <typename T, int N, bool COL, bool X3 = false>

@@ -123,3 +123,40 @@ def test_config4_batch_512_directional_derivative(torch, ag):
     fd = (loss64(h * v) - loss64(-h * v)) / (2 * h)
     got = float(theta.grad.numpy() @ v)
     assert abs(got - fd) <= 1e-4 * max(abs(fd), 1e-3 * loss.item()), (got, fd)
+
+
+@pytest.mark.parametrize("override", [4, 5])
+def test_lc_gradients_match_oracle_finite_differences(torch, ag, override):
+    """The LC-NsDLCT (rank-one gauge h of eqs. LC08 / LC10, a closed form in
+    M): dLoss/dx and dLoss/dtheta against the oracle's LC chain
+    (``oracle.fast``), central differences with h = 1e-6."""
+    from oracle import fast
+    M0 = next(synth.symplectic_candidates(13))
+    Nx, Ny, dx, dy = 32, 48, 0.45, 0.6
+    axis = override - 4
+    x = synth.complex_normal((2, Nx, Ny), seed=3)
+    y = synth.complex_normal((2, Nx, Ny), seed=4)
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    yt = torch.from_numpy(y).cuda()
+    theta = torch.zeros(10, dtype=torch.float64, requires_grad=True)
+    G = ag.nsdlct(xt, theta, M0, dx, dy, precision="c128", type_override=override)
+    loss = (G - yt).abs().pow(2).sum()
+    loss.backward()
+    p0 = fast.lc_plan(M0, Nx, Ny, dx, dy, axis=axis)
+    ref_gx = np.stack([2 * fast.inverse(p0, fast.forward(p0, xi) - yi) for xi, yi in zip(x, y)])
+    assert chain.rel_l2(xt.grad.cpu().numpy(), ref_gx) <= 1e-9
+
+    def oloss(M):
+        p = fast.lc_plan(M, Nx, Ny, dx, dy, axis=axis)
+        return sum(float(np.sum(np.abs(fast.forward(p, xi) - yi) ** 2)) for xi, yi in zip(x, y))
+
+    # The LC stage matrices of this draw are large, so the loss curves more
+    # strongly than in the HA test: h = 1e-6 (FP64 rounding stays ~1e-10).
+    h = 1e-6
+    fd = np.zeros(10)
+    for i in range(10):
+        e = np.zeros(10)
+        e[i] = h
+        fd[i] = (oloss(_M(M0, e)) - oloss(_M(M0, -e))) / (2 * h)
+    got = theta.grad.numpy()
+    assert np.linalg.norm(got - fd) <= 2e-6 * np.linalg.norm(fd), (got, fd)

@@ -129,3 +129,33 @@ def test_1024_against_oracle(torch, nl, typ):
     g = synth.complex_normal((N, N), seed=1)
     G = p.forward(torch.from_numpy(g).to(torch.complex64).cuda()).cpu().numpy()
     assert chain.rel_l2(G, fast.forward(_oracle_plan(typ, M, N, N, d), g)) <= 1e-5
+
+
+def test_batched_and_split_paths_accept_reduced_types(torch, nl):
+    """The ragged batch and the split-precision kernels run the five-slot
+    form of a reduced chain: same transform as the three-pass schedule."""
+    N = 256
+    d = math.sqrt(2 * math.pi / N)
+    M3, M5 = _cmccm_matrix(21), _lc_matrix(21)
+    plans = [nl.Plan(M3, N, N, d, d, type_override=3), nl.Plan(M5, N, N, d, d, type_override=5),
+             nl.Plan(M5, 128, 128, d, d, type_override=5)]
+    b = nl.Batch(plans)
+    x = torch.from_numpy(synth.complex_normal((b.total,), seed=3)).to(torch.complex64).cuda()
+    y = torch.empty_like(x)
+    b.forward(x, y)
+    off = 0
+    for p in plans:
+        st = p.stages()
+        n = p.Nx * p.Ny
+        ref = p.forward(x[off:off + n].view(p.Nx, p.Ny).contiguous())
+        got = y[off:off + n].view(p.Nx, p.Ny)
+        assert (torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref)).item() <= 1e-5, st["type"]
+        off += n
+    for p in plans[:2]:
+        st = p.stages()
+        ps = nl.Plan.from_stages(st["type"], st["mats"], N, N, d, d, "c64_split_bf16")
+        assert ps.passes() == 5
+        xi = torch.from_numpy(synth.complex_normal((N, N), seed=4)).to(torch.complex64).cuda()
+        ref = p.forward(xi)
+        got = ps.forward(xi)
+        assert (torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref)).item() <= 1e-4
