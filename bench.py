@@ -219,6 +219,28 @@ def bench_reduced(nl, torch, M, N, d, ins, outs, K):
     return out
 
 
+def bench_general_sizes(nl, torch, synth, draw_matrix, K=200):
+    """One image per call at side lengths without a native line FFT (the
+    paper's 100 x 100 and 165 x 165 grids, and a prime 257): Bluestein line
+    DFTs, complex64."""
+    out = {}
+    for N in (100, 165, 257):
+        d = math.sqrt(2 * math.pi / N)
+        _, M, p = draw_matrix(1, N, d, nl)
+        x = torch.randn(N, N, dtype=torch.complex64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            p.forward(x, out=y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            p.forward(x, out=y)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / K
+        out[f"{N}x{N}"] = {"us_per_transform": sec * 1e6, "NsLCT_per_s": 1 / sec}
+    return out
+
+
 def bench_backward(nl, torch, synth, np, count=32, N=512, reps=10):
     """One training step of loss = ||NsDLCT_M(theta)(x) - y||^2 on `count`
     images of N x N (y: the transform under a perturbed matrix): forward,
@@ -283,6 +305,7 @@ def main():
     ap.add_argument("--conc", type=int, default=1, help="also time 8 transforms per launch")
     ap.add_argument("--backward", type=int, default=1, help="also time the 32 x 512^2 fwd+bwd step")
     ap.add_argument("--reduced", type=int, default=1, help="also time the three-pass LC / CM-CC-CM schedules")
+    ap.add_argument("--general", type=int, default=1, help="also time 100^2 / 165^2 / 257^2 (Bluestein lines)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched and "
@@ -379,6 +402,7 @@ def main():
         del x8, y8
 
     reduced = bench_reduced(nl, torch, M, N, d, ins, outs, K) if args.reduced else None
+    general = bench_general_sizes(nl, torch, synth, draw_matrix) if args.general else None
     batched = bench_batched(nl, torch, synth, np) if args.batched else None
     split = bench_split(nl, torch, synth, np) if args.split else None
     bwd = bench_backward(nl, torch, synth, np) if args.backward else None
@@ -437,6 +461,8 @@ def main():
                                  "note": "8 independent 1024x1024 transforms per launch (grid.y = 8)"}
     if reduced:
         result["reduced_schedules_1024"] = reduced
+    if general:
+        result["general_sizes_c64"] = general
     if batched:
         result["batched_ragged"] = batched
     if split:

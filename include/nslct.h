@@ -42,8 +42,14 @@
  *   kernel shows up at the next synchronising HIP call.
  *
  * Sizes
- *   Nx, Ny are 2^k from 2 to 4096 or 3 * 2^k from 6 to 768 (NSLCT_E_SIZE
- *   otherwise).
+ *   Nx, Ny are any length from 2 to 2048, or 2^k up to 4096 (NSLCT_E_SIZE
+ *   otherwise).  2^k and 3 * 2^k (up to 768) run native mixed-radix line
+ *   FFTs; every other length runs Bluestein's chirp-z form of its line DFT
+ *   on a power-of-two line of at least 2N - 1 samples (about four times the
+ *   arithmetic; its tables are computed on the host and uploaded on the
+ *   first transform of that length on a device, so that first call must not
+ *   be inside a stream capture).  The batch, backward and split-precision
+ *   entry points take native lengths only.
  */
 #ifndef NSLCT_H
 #define NSLCT_H

@@ -28,6 +28,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <array>
 #include <mutex>
 #include <vector>
 #include <new>
@@ -787,14 +788,275 @@ hipError_t launch_batched_group(int N, const BatchArgs<T>& a, int grid, hipStrea
 
 template <typename T>
 hipError_t launch_pass_typed(const PlanData& d, int dir, int pass, int count, const void* in, void* out,
-                             hipStream_t s) {
-    const PassArgs<T> a = pass_args<T>(d, dir, pass, in, out);
-    const bool col = (pass == 1 || pass == 3);
-    return col ? launch_n<T, true>(d.Nx, a, count, s) : launch_n<T, false>(d.Ny, a, count, s);
-}
+                             hipStream_t s);
 
 template <int KIND, bool COL>
 hipError_t launch_split_n(int N, const PassArgs<float>& a, int count, hipStream_t s);
+
+// ---------------------------------------------------------------- Bluestein
+// Line lengths N without a native plan (any N <= 2048 that is not 2^k or
+// 3 * 2^k): each N-point line DFT is Bluestein's chirp-z form on an M-point
+// line, M the smallest power of two >= 2N - 1.  With kn = (k^2 + n^2 -
+// (k - n)^2) / 2, a DFT of exponent sign S is
+//   X_k = c_k sum_n (x_n c_n) b_(k-n),  c_n = exp(S j pi n^2 / N),
+//   b_m = exp(-S j pi m^2 / N),
+// a linear convolution evaluated as FFT_M -> multiply by FFT_M(b) / M ->
+// inverse FFT_M.  The chirp phases come from the exact integer n^2 mod 2N.
+// FFT_M(b) / M for S = -1 and S = +1 is tabulated once per (device, N,
+// precision) in FP64 on the host.
+template <typename T>
+struct BsArgs {
+    int N;               // line length
+    const cplx<T>* tab;  // [0, M): S = -1, [M, 2M): S = +1
+};
+
+bool native_line(int n) {
+    if (n >= 2 && n <= 4096 && (n & (n - 1)) == 0) return true;
+    if (n % 3 == 0 && n >= 6 && n <= 768) {
+        const int m = n / 3;
+        return (m & (m - 1)) == 0;
+    }
+    return false;
+}
+
+int bluestein_length(int n) {
+    int m = 1;
+    while (m < 2 * n - 1) m <<= 1;
+    return m;
+}
+
+std::mutex g_bs_mu;
+std::vector<std::pair<std::array<int, 4>, void*>> g_bs;  // (device, N, M, fp64) -> table
+
+int bs_tables(int N, int M, bool dbl, const void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    const std::array<int, 4> key{dev, N, M, dbl ? 1 : 0};
+    std::lock_guard<std::mutex> lk(g_bs_mu);
+    for (const auto& kv : g_bs)
+        if (kv.first == key) {
+            *out = kv.second;
+            return NSLCT_OK;
+        }
+    // b_m for S = -1 (exp(+j pi m^2 / N)) at m and M - m; B = FFT_M(b).
+    const double pi = 3.14159265358979323846;
+    std::vector<double> br(M, 0.0), bi(M, 0.0), cr(M), ci(M);
+    for (int m = 0; m < N; ++m) {
+        const long long r = ((long long)m * m) % (2LL * N);
+        br[m] = std::cos(pi * (double)r / N);
+        bi[m] = std::sin(pi * (double)r / N);
+        if (m > 0) {
+            br[M - m] = br[m];
+            bi[M - m] = bi[m];
+        }
+    }
+    for (int k = 0; k < M; ++k) {
+        cr[k] = std::cos(2 * pi * k / M);
+        ci[k] = -std::sin(2 * pi * k / M);
+    }
+    std::vector<double> Br(M), Bi(M);
+    for (int p = 0; p < M; ++p) {
+        double sr = 0, si = 0;
+        for (int m = 0; m < M; ++m) {
+            if (m >= N && m <= M - N) continue;  // b is zero there
+            const int k = (int)(((long long)p * m) % M);
+            sr += br[m] * cr[k] - bi[m] * ci[k];
+            si += br[m] * ci[k] + bi[m] * cr[k];
+        }
+        Br[p] = sr / M;
+        Bi[p] = si / M;
+    }
+    const size_t elem = dbl ? sizeof(cplx<double>) : sizeof(cplx<float>);
+    std::vector<unsigned char> host(2 * (size_t)M * elem);
+    for (int p = 0; p < M; ++p)
+        for (int sidx = 0; sidx < 2; ++sidx) {
+            const double re = Br[p], im = sidx == 0 ? Bi[p] : -Bi[p];  // S = +1: conjugate (b is even)
+            const size_t at = ((size_t)sidx * M + p);
+            if (dbl)
+                reinterpret_cast<cplx<double>*>(host.data())[at] = {re, im};
+            else
+                reinterpret_cast<cplx<float>*>(host.data())[at] = {(float)re, (float)im};
+        }
+    void* dptr = nullptr;
+    e = hipMalloc(&dptr, host.size());
+    if (e == hipSuccess) e = hipMemcpy(dptr, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (dptr) (void)hipFree(dptr);
+        return fail(NSLCT_E_HIP, std::string("Bluestein table: ") + hipGetErrorString(e));
+    }
+    g_bs.push_back({key, dptr});
+    *out = dptr;
+    return NSLCT_OK;
+}
+
+// exp(S j 2 pi r / (2N)) * scale, r = n^2 mod 2N (exact), in the working precision.
+__device__ __forceinline__ cplx<float> bs_chirp(int r, int twoN, int S, float scale) {
+    float t = (float)r / (float)twoN;
+    if (t >= 0.5f) t -= 1.f;
+    return {__builtin_amdgcn_cosf(t) * scale, (float)S * __builtin_amdgcn_sinf(t) * scale};
+}
+__device__ __forceinline__ cplx<double> bs_chirp(int r, int twoN, int S, double scale) {
+    double sn, cs;
+    sincospi(2.0 * (double)r / (double)twoN, &sn, &cs);
+    return {cs * scale, (double)S * sn * scale};
+}
+
+// One pass on lines of length N through M-point Bluestein line DFTs; the
+// pass structure ([pre] DFT [mid] [DFT], remaps, centring) is that of
+// pass_body, with every sample access restricted to positions < N.
+template <typename T, int M, bool COL, int LINES>
+__global__ void __launch_bounds__(LinePlan<M>::TPL* LINES) nslct_bs_pass(PassArgs<T> a, BsArgs<T> bs) {
+    constexpr int TPL = LinePlan<M>::TPL;
+    using F = LineFFT<T, M, TPL>;
+    constexpr int E = F::E;
+    constexpr int R0 = F::R0;
+    constexpr int LL = lds_line_elems<M>();
+    __shared__ cplx<T> lds_all[LINES * LL];
+
+    const int N = bs.N, twoN = 2 * N;
+    const int tid = threadIdx.x;
+    const int slot = tid / TPL;
+    const int t = tid % TPL;
+    const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int line = tile * LINES + slot;
+    const int nl = a.nlines;
+    const bool active = line < nl;
+    cplx<T>* lds = lds_all + slot * LL;
+    const cplx<T>* __restrict__ tab = twiddles<T>();
+    const size_t img_off = (size_t)blockIdx.y * a.img_stride;
+    const cplx<T>* __restrict__ in = a.in + img_off;
+    cplx<T>* __restrict__ out = a.out + img_off;
+
+    cplx<T> w[F::TW];
+    F::preload(w, t, tab);
+    auto pos = [&](int r) { return t + TPL * (r / R0) + (r % R0) * (M / R0); };
+    auto to_store = [&](int p) { const int q = p + N / 2; return q >= N ? q - N : q; };
+    auto addr = [&](int p) { return COL ? (size_t)p * nl + line : (size_t)line * N + p; };
+
+    cplx<T> v[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int p = pos(r);
+        v[r] = (active && p < N) ? in[addr(a.load_remap ? to_store(p) : p)] : cplx<T>{0, 0};
+    }
+
+    const int lc = a.line_centered ? line - nl / 2 : (line >= (nl + 1) / 2 ? line - nl : line);
+    const uint64_t l64 = (uint64_t)(int64_t)lc;
+    auto chirp = [&](const ChirpArg& c, T scale) {
+        const uint64_t A = (COL ? c.c22 : c.c11) * (l64 * l64);
+        const uint64_t Bc = c.c12 * l64;
+        const uint64_t Q = COL ? c.c11 : c.c22;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int p = pos(r);
+            const int64_t ks = p < (N + 1) / 2 ? p : p - N;
+            const uint64_t k64 = (uint64_t)ks;
+            const uint64_t ph = A + Bc * k64 + Q * (k64 * k64);
+            if (p < N) v[r] = cmul(v[r], turns_cs(ph, scale));
+        }
+    };
+    // N-point DFT of exponent sign S of the positions < N (natural order in
+    // and out, zero beyond N).
+    auto bdft = [&](int S) {
+        const cplx<T>* __restrict__ bt = bs.tab + (S < 0 ? 0 : M);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int p = pos(r);
+            const int rr = (int)(((long long)p * p) % twoN);
+            v[r] = p < N ? cmul(v[r], bs_chirp(rr, twoN, S, (T)1)) : cplx<T>{0, 0};
+        }
+        F::template dft<-1>(v, lds, t, w, tab);
+#pragma unroll
+        for (int r = 0; r < E; ++r) v[r] = cmul(v[r], bt[pos(r)]);
+        F::template dft<+1>(v, lds, t, w, tab);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int p = pos(r);
+            const int rr = (int)(((long long)p * p) % twoN);
+            v[r] = p < N ? cmul(v[r], bs_chirp(rr, twoN, S, (T)1)) : cplx<T>{0, 0};
+        }
+    };
+
+    if (a.pre.on) chirp(a.pre, (T)1);
+    const int ndft = a.has_t2 ? 2 : 1;
+#pragma nounroll
+    for (int k = 0; k < ndft; ++k) {
+        bdft(k == 0 ? a.sign1 : a.sign2);
+        if (k == 0 && a.mid_on) {
+            if (a.mid.on) {
+                chirp(a.mid, a.scale);
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; ++r) v[r] = {v[r].re * a.scale, v[r].im * a.scale};
+            }
+        }
+    }
+
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int p = pos(r);
+            if (p < N) out[addr(a.store_remap ? to_store(p) : p)] = v[r];
+        }
+    }
+}
+
+template <typename T, int M, bool COL>
+hipError_t launch_bs_t(const PassArgs<T>& a, const BsArgs<T>& b, int count, hipStream_t s) {
+    constexpr int L = COL ? col_lines<T, M>() : row_lines<T, M>();
+    static_assert(L * lds_line_elems<M>() * sizeof(cplx<T>) <= 160 * 1024, "LDS budget");
+    hipLaunchKernelGGL((nslct_bs_pass<T, M, COL, L>), dim3((a.nlines + L - 1) / L, count),
+                       dim3(LinePlan<M>::TPL * L), 0, s, a, b);
+    return hipGetLastError();
+}
+
+template <typename T, bool COL>
+hipError_t launch_bs_n(int M, const PassArgs<T>& a, const BsArgs<T>& b, int count, hipStream_t s) {
+    switch (M) {
+        case 8: return launch_bs_t<T, 8, COL>(a, b, count, s);
+        case 16: return launch_bs_t<T, 16, COL>(a, b, count, s);
+        case 32: return launch_bs_t<T, 32, COL>(a, b, count, s);
+        case 64: return launch_bs_t<T, 64, COL>(a, b, count, s);
+        case 128: return launch_bs_t<T, 128, COL>(a, b, count, s);
+        case 256: return launch_bs_t<T, 256, COL>(a, b, count, s);
+        case 512: return launch_bs_t<T, 512, COL>(a, b, count, s);
+        case 1024: return launch_bs_t<T, 1024, COL>(a, b, count, s);
+        case 2048: return launch_bs_t<T, 2048, COL>(a, b, count, s);
+        case 4096: return launch_bs_t<T, 4096, COL>(a, b, count, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Bluestein tables of every non-native axis of a plan on the current device
+// (computed and uploaded on first use).
+int prepare_plan_tables(const PlanData& d) {
+    const bool split = d.precision == NSLCT_C64_SPLIT_F16 || d.precision == NSLCT_C64_SPLIT_BF16;
+    if (split) return NSLCT_OK;
+    for (int n : {d.Nx, d.Ny}) {
+        if (native_line(n)) continue;
+        const void* tabp = nullptr;
+        const int rc = bs_tables(n, bluestein_length(n), d.precision == NSLCT_C128, &tabp);
+        if (rc) return rc;
+    }
+    return NSLCT_OK;
+}
+
+template <typename T>
+hipError_t launch_pass_typed(const PlanData& d, int dir, int pass, int count, const void* in, void* out,
+                             hipStream_t s) {
+    const PassArgs<T> a = pass_args<T>(d, dir, pass, in, out);
+    const bool col = (pass == 1 || pass == 3);
+    const int N = col ? d.Nx : d.Ny;
+    if (!native_line(N)) {
+        const void* tabp = nullptr;
+        if (bs_tables(N, bluestein_length(N), sizeof(T) == 8, &tabp) != NSLCT_OK) return hipErrorInvalidValue;
+        const BsArgs<T> b{N, (const cplx<T>*)tabp};
+        const int M = bluestein_length(N);
+        return col ? launch_bs_n<T, true>(M, a, b, count, s) : launch_bs_n<T, false>(M, a, b, count, s);
+    }
+    return col ? launch_n<T, true>(d.Nx, a, count, s) : launch_n<T, false>(d.Ny, a, count, s);
+}
 
 // Passes of the single-image path: the three-pass schedule of a reduced
 // chain (CM-CC-CM, LC) in c64 / c128, else the five-pass chain.
@@ -870,6 +1132,7 @@ int run_chain(nslct_plan_t plan, int dir, int count, const void* in, void* out, 
     if (rc) return rc;
     if (count == 0) return NSLCT_OK;
     rc = ensure_device_ready();
+    if (!rc) rc = prepare_plan_tables(plan->d);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int np = plan_passes(plan->d);
@@ -1119,6 +1382,7 @@ int nslct_launch_pass(nslct_plan_t plan, int direction, int pass, int count, con
     int rc = check_ptrs(in, out);
     if (rc) return rc;
     rc = ensure_device_ready();
+    if (!rc) rc = prepare_plan_tables(plan->d);
     if (rc) return rc;
     hipError_t e = launch_pass(plan->d, direction, pass, count, in, out, (hipStream_t)stream);
     if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("pass launch: ") + hipGetErrorString(e));

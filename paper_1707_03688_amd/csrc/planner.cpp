@@ -449,25 +449,31 @@ GaugeOut solve(const Gauge& g, double mmax, const double* start = nullptr) {
     return out;
 }
 
-uint64_t turns_fixed(double kappa) {
-    // frac(kappa / 2 pi) as a 64-bit fixed-point fraction of a turn.
-    const double t = kappa / kTwoPi;
-    double f = t - std::floor(t);
-    if (!(f < 1.0)) f = 0.0;
-    return (uint64_t)std::ldexp(f, 64);
+uint64_t turns_fixed(long double kappa) {
+    // frac(kappa / 2 pi) as a 64-bit fixed-point fraction of a turn.  The
+    // host's long double (64-bit significand) keeps the coefficient's own
+    // rounding near 2^-64 turns: the device multiplies it by exact squared
+    // sample indices (up to ~2^22), which would lift a 53-bit coefficient's
+    // rounding to ~1e-10 turns at N = 2048.
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    const long double t = kappa / two_pi;
+    long double f = t - floorl(t);
+    if (!(f < 1.0L)) f = 0.0L;
+    return (uint64_t)ldexpl(f, 64);
 }
 
 ChirpTurns make_turns(const double p[3], double du, double dv) {
     ChirpTurns c;
-    c.c11 = turns_fixed(0.5 * p[0] * du * du);
-    c.c12 = turns_fixed(p[1] * du * dv);
-    c.c22 = turns_fixed(0.5 * p[2] * dv * dv);
+    const long double u = du, v = dv;
+    c.c11 = turns_fixed(0.5L * (long double)p[0] * u * u);
+    c.c12 = turns_fixed((long double)p[1] * u * v);
+    c.c22 = turns_fixed(0.5L * (long double)p[2] * v * v);
     c.nonzero = (p[0] != 0.0 || p[1] != 0.0 || p[2] != 0.0) ? 1 : 0;
     return c;
 }
 
-// Supported line lengths: 2^k (2..4096) and 3 * 2^k (6..768).
-bool supported_size(int n) {
+// Line lengths with a native plan: 2^k (2..4096) and 3 * 2^k (6..768).
+bool native_size(int n) {
     if (n >= 2 && n <= 4096 && (n & (n - 1)) == 0) return true;
     if (n % 3 == 0 && n >= 6 && n <= 768) {
         const int m = n / 3;
@@ -475,6 +481,10 @@ bool supported_size(int n) {
     }
     return false;
 }
+
+// Supported: native lengths, and any other length up to 2048 (Bluestein's
+// chirp-z form on a power-of-two line of at least 2N - 1 samples).
+bool supported_size(int n) { return native_size(n) || (n >= 2 && n <= 2048); }
 
 ProgPass prog_pass(int col, int lr, int sr, int lcn, int ndft, int s0, int s1, int s2) {
     ProgPass q{};
@@ -503,6 +513,8 @@ ProgPass prog_pass(int col, int lr, int sr, int lcn, int ndft, int s0, int s1, i
 // the reversed factors with negated matrices.
 void fill_program(PlanData* p) {
     const nslct_stages& s = p->st;
+    p->prog[0].npass = p->prog[1].npass = 0;
+    if (!native_size(p->Nx) || !native_size(p->Ny)) return;  // Bluestein axes: the five-slot chain
     const double iNx = 1.0 / p->Nx, iNy = 1.0 / p->Ny;
     auto turns = [&](const double* m, double sign, bool freq) {
         double x[3] = {sign * m[0], sign * m[1], sign * m[2]};
@@ -618,7 +630,7 @@ int check_common(int Nx, int Ny, double dx, double dy, const nslct_opts& o, std:
         return NSLCT_E_ARG;
     }
     if (!supported_size(Nx) || !supported_size(Ny)) {
-        *err = "Nx and Ny must be 2^k in [2, 4096] or 3 * 2^k in [6, 768]";
+        *err = "Nx and Ny must be in [2, 2048], or 2^k up to 4096";
         return NSLCT_E_SIZE;
     }
     if (o.precision < NSLCT_C64 || o.precision > NSLCT_C64_SPLIT_BF16) {

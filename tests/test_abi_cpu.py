@@ -55,9 +55,11 @@ def test_error_codes(nl):
     bad = M.copy()
     bad[0, 0] += 1e-3
     assert _cplan(nl, bad) == -2                       # NSLCT_E_NOT_SYMPLECTIC
-    assert _cplan(nl, M, Nx=20) == -4                  # NSLCT_E_SIZE
-    assert _cplan(nl, M, Nx=1536) == -4
-    assert _cplan(nl, M, Nx=12) == 0                   # 3 * 2^k is supported
+    assert _cplan(nl, M, Nx=3000) == -4                # NSLCT_E_SIZE
+    assert _cplan(nl, M, Nx=1) == -4
+    assert _cplan(nl, M, Nx=12) == 0                   # 3 * 2^k: native
+    assert _cplan(nl, M, Nx=20) == 0                   # Bluestein
+    assert _cplan(nl, M, Nx=1536) == 0
     assert _cplan(nl, M, Nx=8192) == -4
     assert _cplan(nl, M, dx=0.0) == -1                 # NSLCT_E_ARG
     assert _cplan(nl, M, dy=float("nan")) == -1
