@@ -87,7 +87,7 @@ def test_gradients_match_oracle_finite_differences(torch, ag, seed):
     assert np.linalg.norm(got - fd) <= 2e-6 * np.linalg.norm(fd), (got, fd)
 
 
-def test_config4_batch_512_directional_derivative(torch, ag):
+def test_batch32_512_directional_derivative(torch, ag):
     """32 x 512 x 512 complex64, y the transform under a perturbed matrix
     (theta* ~ N(0, 0.05)); dLoss/dtheta . v against a central difference of
     the complex128 GPU loss along a random unit direction v; dLoss/dx against

@@ -88,7 +88,7 @@ def test_forward_inverse_match_oracle_c128(torch, nl, shape, typ):
     assert chain.rel_l2(Gi, chain.inverse(po, g)) <= TOL["c128"]
 
 
-def test_config0_c128_against_dense_operator(torch, nl):
+def test_64x64_c128_against_dense_operator(torch, nl):
     """64 x 64 complex128, unit spacing, draws of the symplectic generator:
     GPU vs the O(N^4) dense-operator evaluation (eq. self12) <= 1e-11."""
     for M in _draws(0, 3):
@@ -101,7 +101,7 @@ def test_config0_c128_against_dense_operator(torch, nl):
 
 
 @pytest.mark.parametrize("field", ["normal", "random_phase"])
-def test_config1_1024_c64_and_reconstruction(torch, nl, field):
+def test_1024_c64_parity_and_reconstruction(torch, nl, field):
     """1024 x 1024 complex64 with spacing sqrt(2 pi / 1024), i.i.d. normal
     samples or the Gaussian-windowed random-phase field: full-image parity
     with the oracle, and forward -> inverse reconstruction."""

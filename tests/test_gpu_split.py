@@ -54,7 +54,7 @@ def test_split_matches_oracle(torch, nl, precision, shape):
     assert chain.rel_l2(back, g) <= 1e-4
 
 
-def test_config3_batch_4096_all_precisions(torch, nl):
+def test_batch8_4096_all_precisions(torch, nl):
     """8 images of 4096 x 4096, one matrix each: split FP16 and BF16 <= 1e-4,
     FP32 <= 1e-5 per output, all against the complex128 GPU path."""
     N = 4096
