@@ -420,6 +420,9 @@ struct LineFFT {
     }
 
     // Stage-s outputs to LDS, then stage-(s+1) inputs back to registers.
+    // lds_pad(p + m) = lds_pad(p) + m + m / 16 for m a multiple of 16 (p >= 0),
+    // so where the index steps are multiples of 16 every access of a loop is
+    // an immediate offset from one padded base; otherwise each is padded.
     template <int Ns, int R, int Rn>
     __device__ __forceinline__ static void exchange(cplx<T>* v, cplx<T>* lds, int t) {
 #pragma unroll
@@ -427,15 +430,34 @@ struct LineFFT {
             const int j = t + TPL * i;
             const int k = j % Ns;
             const int base = (j / Ns) * Ns * R + k;
+            if constexpr (Ns % 16 == 0) {
+                const int pb = lds_pad(base);
 #pragma unroll
-            for (int q = 0; q < R; ++q) lds[lds_pad(base + q * Ns)] = v[i * R + q];
+                for (int q = 0; q < R; ++q) lds[pb + q * (Ns + Ns / 16)] = v[i * R + q];
+            } else if constexpr (Ns == 1 && R == 16) {
+                // base = 16 j: the 16 outputs share one padding group.
+                const int pb = lds_pad(base);
+#pragma unroll
+                for (int q = 0; q < R; ++q) lds[pb + q] = v[i * R + q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < R; ++q) lds[lds_pad(base + q * Ns)] = v[i * R + q];
+            }
         }
         sync();
+        constexpr int st = N / Rn;
+        const int pt = lds_pad(t);
 #pragma unroll
         for (int i = 0; i < E / Rn; ++i) {
             const int j = t + TPL * i;
+            if constexpr (st % 16 == 0 && TPL % 16 == 0) {
+                const int pj = pt + i * (TPL + TPL / 16);
 #pragma unroll
-            for (int q = 0; q < Rn; ++q) v[i * Rn + q] = lds[lds_pad(j + q * (N / Rn))];
+                for (int q = 0; q < Rn; ++q) v[i * Rn + q] = lds[pj + q * (st + st / 16)];
+            } else {
+#pragma unroll
+                for (int q = 0; q < Rn; ++q) v[i * Rn + q] = lds[lds_pad(j + q * st)];
+            }
         }
         sync();
     }
