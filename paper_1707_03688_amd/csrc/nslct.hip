@@ -506,6 +506,172 @@ hipError_t launch_n(int N, const PassArgs<T>& a, int count, hipStream_t s) {
     }
 }
 
+// ------------------------------------------- 4096-long columns, in three steps
+// A column pass over 4096-long columns (FFT -> pointwise product -> inverse
+// FFT) as three launches over 64 x 64 blocks of each column, so that every
+// global access covers whole 128-byte row segments instead of the 16-byte
+// segments of a 2-column whole-column tile, which waste most of every L2
+// request.  With n = n1 + 64 n2,
+// k = k2 + 64 k1, m = m1 + 64 m2 (all in [0, 64)) and W = exp(S 2 pi j / 4096):
+//   A: for each n1, Y[k2] = W^(n1 k2) sum_n2 x[n1 + 64 n2] w64^(n2 k2),
+//      stored at row n1 + 64 k2 (rows = n1 mod 64, a strided gather);
+//   B: for each k2 (64 contiguous rows): X[k2 + 64 k1] = sum_n1 Y w64^(n1 k1)
+//      is the first line DFT; the pointwise product at k; then
+//      U[m1] = W'^(k2 m1) sum_k1 X[k2 + 64 k1] w64'^(k1 m1) (second sign),
+//      stored at row m1 + 64 k2;
+//   C: for each m1, Z[m1 + 64 m2] = sum_k2 U w64'^(k2 m2), the second line
+//      DFT, stored at row m (with the FFT -> centred remap if asked).
+// Each step is in place over a disjoint set of rows and columns per
+// workgroup.  A workgroup covers 128 bytes of every row it touches (16
+// complex64 or 8 complex128 columns) so that no cache line is split between
+// workgroups (consecutive workgroups run on different XCDs); each wavefront
+// holds 8 columns x 8 threads, each thread 8 of a column's 64 samples.
+template <typename T>
+constexpr int fs_cols() {
+    return 128 / (int)sizeof(cplx<T>);
+}
+
+// x * exp(S 2 pi j e / 4096) from the forward-sign table (W_12288).
+template <typename T>
+__device__ __forceinline__ cplx<T> fs_twiddle(cplx<T> x, int e, int S, const cplx<T>* __restrict__ tab) {
+    cplx<T> w = tab[(e & 4095) * (kTwiddleN / 4096)];
+    if (S > 0) w.im = -w.im;
+    return cmul(x, w);
+}
+
+// 64-point line DFT of sign S over the registers (positions t + 8 i), the
+// sign -1 case as the conjugate of the sign +1 DFT of the conjugate.
+template <typename T>
+__device__ __forceinline__ void fs_dft64(cplx<T>* v, cplx<T>* lds, int t, const cplx<T>* w,
+                                         const cplx<T>* __restrict__ tab, int S) {
+    using F = LineFFT<T, 64, 8>;
+    if (S < 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r].im = -v[r].im;
+    }
+    F::template dft<+1>(v, lds, t, w, tab);
+    if (S < 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r].im = -v[r].im;
+    }
+}
+
+// STEP 0 = A, 1 = B, 2 = C.  blockIdx.x = column block + ncb * (block row
+// index n1 / k2 / m1), blockIdx.y = image.
+template <typename T, int STEP>
+__global__ void __launch_bounds__(8 * fs_cols<T>()) nslct_col4096_step(PassArgs<T> a, int ncb) {
+    using F = LineFFT<T, 64, 8>;
+    static_assert(F::E == 8 && F::R0 == 8, "64-point plan: 8 threads x 8 samples");
+    constexpr int N = 4096;
+    constexpr int CB = fs_cols<T>();
+    __shared__ cplx<T> lds_all[CB * lds_line_elems<64>()];
+    const int tid = threadIdx.x;
+    const int cl = 8 * (tid / 64) + tid % 8;  // column within the block
+    const int t = (tid % 64) / 8;             // thread within the column's 64-point line
+    const int cb = blockIdx.x % ncb;
+    const int j = blockIdx.x / ncb;  // n1 (A), k2 (B) or m1 (C)
+    const int nl = a.nlines;
+    const int c = cb * CB + cl;
+    const bool active = c < nl;
+    const size_t img = (size_t)blockIdx.y * a.img_stride;
+    const cplx<T>* __restrict__ in = (STEP == 0 ? a.in : a.out) + img;
+    cplx<T>* __restrict__ out = a.out + img;
+    cplx<T>* lds = lds_all + cl * lds_line_elems<64>();
+    const cplx<T>* __restrict__ tab = twiddles<T>();
+    cplx<T> w[F::TW];
+    F::preload(w, t, tab);
+
+    // Register i holds block position t + 8 i; its image row:
+    auto row = [&](int i) {
+        const int b = t + 8 * i;
+        if constexpr (STEP == 0) {
+            const int n = j + 64 * b;
+            return a.load_remap ? fft_to_store<N>(n) : n;
+        } else if constexpr (STEP == 1) {
+            return 64 * j + b;
+        } else {
+            return j + 64 * b;
+        }
+    };
+    cplx<T> v[8];
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = in[(size_t)row(i) * nl + c];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = {0, 0};
+    }
+
+    if constexpr (STEP == 0) {
+        fs_dft64(v, lds, t, w, tab, a.sign1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = fs_twiddle(v[i], j * (t + 8 * i), a.sign1, tab);
+    } else if constexpr (STEP == 1) {
+        fs_dft64(v, lds, t, w, tab, a.sign1);
+        // Register i now holds k1 = t + 8 i, i.e. FFT index k = j + 64 k1.
+        const int lc = a.line_centered ? c - nl / 2 : (c >= (nl + 1) / 2 ? c - nl : c);
+        const uint64_t l64 = (uint64_t)(int64_t)lc;
+        const uint64_t A0 = a.mid.c22 * (l64 * l64);
+        const uint64_t Bc = a.mid.c12 * l64;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (a.mid.on) {
+                const int k = j + 64 * (t + 8 * i);
+                const int64_t e = k < N / 2 ? k : k - N;
+                const uint64_t e64 = (uint64_t)e;
+                const uint64_t ph = A0 + Bc * e64 + a.mid.c11 * (e64 * e64);
+                v[i] = cmul(v[i], turns_cs(ph, a.scale));
+            } else {
+                v[i] = {v[i].re * a.scale, v[i].im * a.scale};
+            }
+        }
+        fs_dft64(v, lds, t, w, tab, a.sign2);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = fs_twiddle(v[i], j * (t + 8 * i), a.sign2, tab);
+    } else {
+        fs_dft64(v, lds, t, w, tab, a.sign2);
+    }
+
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int b = t + 8 * i;
+            int r;
+            if constexpr (STEP == 0) {
+                r = j + 64 * b;
+            } else if constexpr (STEP == 1) {
+                r = 64 * j + b;
+            } else {
+                const int m = j + 64 * b;
+                r = a.store_remap ? fft_to_store<N>(m) : m;
+            }
+            out[(size_t)r * nl + c] = v[i];
+        }
+    }
+}
+
+// The column pass of the five-slot chain (first DFT, pointwise product,
+// second DFT; no product before the first DFT) on 4096-long columns.
+template <typename T>
+bool col4096_applies(const PassArgs<T>& a, int N) {
+    return N == 4096 && a.has_t2 && a.mid_on && !a.pre.on;
+}
+
+template <typename T>
+hipError_t launch_col4096(const PassArgs<T>& a, int count, hipStream_t s) {
+    constexpr int CB = fs_cols<T>();
+    const int ncb = (a.nlines + CB - 1) / CB;
+    const dim3 grid(ncb * 64, count), block(8 * CB);
+    hipLaunchKernelGGL((nslct_col4096_step<T, 0>), grid, block, 0, s, a, ncb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((nslct_col4096_step<T, 1>), grid, block, 0, s, a, ncb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((nslct_col4096_step<T, 2>), grid, block, 0, s, a, ncb);
+    return hipGetLastError();
+}
+
 // Per-device one-time setup (twiddle tables).
 std::mutex g_init_mu;
 bool g_inited[64] = {};
@@ -1111,6 +1277,7 @@ hipError_t launch_pass_typed(const PlanData& d, int dir, int pass, int count, co
         const int M = bluestein_length(N);
         return col ? launch_bs_n<T, true>(M, a, b, count, s) : launch_bs_n<T, false>(M, a, b, count, s);
     }
+    if (col && col4096_applies(a, N)) return launch_col4096(a, count, s);
     return col ? launch_n<T, true>(d.Nx, a, count, s) : launch_n<T, false>(d.Ny, a, count, s);
 }
 

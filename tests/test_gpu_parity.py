@@ -75,6 +75,34 @@ def test_forward_inverse_match_oracle_c64(torch, nl, shape, typ):
     assert chain.rel_l2(Gi, chain.inverse(po, g)) <= TOL["c64"]
 
 
+@pytest.mark.parametrize("shape,precision", [((4096, 13), "c64"), ((4096, 24), "c64"),
+                                             ((4096, 8), "c128"), ((4096, 5), "c128")])
+def test_4096_long_columns_match_oracle(torch, nl, shape, precision):
+    """Columns of length 4096 run as three launches over 64 x 64 blocks of 8
+    columns (column counts that are and are not a multiple of 8): forward and
+    inverse against the oracle, in place, and three images in one call equal
+    to three calls.  complex128 runs at the spacing sqrt(2 pi / N): at 0.7 the
+    chirp phases reach 1e6 rad, where the FP64 oracle's own phase rounding
+    (one ulp of 1e6 is 1.2e-10) exceeds the 1e-11 bar."""
+    Nx, Ny = shape
+    M = _draws(23, 1)[0]
+    dx, dy = (0.7, 0.45) if precision == "c64" else (math.sqrt(2 * math.pi / Nx),) * 2
+    po, pg = _pair(nl, M, Nx, Ny, dx, dy, precision=precision)
+    g = synth.complex_normal(shape, seed=Ny)
+    x = _to_gpu(torch, g, precision)
+    G = pg.forward(x).cpu().numpy()
+    assert chain.rel_l2(G, chain.forward(po, g)) <= TOL[precision]
+    Gi = pg.inverse(x).cpu().numpy()
+    assert chain.rel_l2(Gi, chain.inverse(po, g)) <= TOL[precision]
+    y = x.clone()
+    pg.forward(y, out=y)
+    assert np.array_equal(y.cpu().numpy(), G)
+    gs = np.stack([synth.complex_normal(shape, seed=Ny + k) for k in range(3)])
+    Gb = pg.forward(_to_gpu(torch, gs, precision)).cpu().numpy()
+    for k in range(3):
+        assert np.array_equal(Gb[k], pg.forward(_to_gpu(torch, gs[k], precision)).cpu().numpy())
+
+
 @pytest.mark.parametrize("shape", [(64, 64), (16, 32), (8, 128), (256, 256), (2, 2), (96, 48), (384, 24)])
 @pytest.mark.parametrize("typ", [1, 2])
 def test_forward_inverse_match_oracle_c128(torch, nl, shape, typ):
