@@ -434,11 +434,20 @@ struct LineFFT {
                 const int pb = lds_pad(base);
 #pragma unroll
                 for (int q = 0; q < R; ++q) lds[pb + q * (Ns + Ns / 16)] = v[i * R + q];
-            } else if constexpr (Ns == 1 && R == 16) {
-                // base = 16 j: the 16 outputs share one padding group.
+            } else if constexpr (Ns == 1 && 16 % R == 0) {
+                // base = R j with R | 16: the R outputs share one padding group.
                 const int pb = lds_pad(base);
 #pragma unroll
                 for (int q = 0; q < R; ++q) lds[pb + q] = v[i * R + q];
+            } else if constexpr (16 % Ns == 0 && R > 16 / Ns) {
+                // Offsets q Ns repeat modulo 16 with period P = 16 / Ns: one
+                // padded base per residue q0 < P, then steps of 16.
+                constexpr int P = 16 / Ns;
+                int pb[P];
+#pragma unroll
+                for (int q0 = 0; q0 < P; ++q0) pb[q0] = lds_pad(base + q0 * Ns);
+#pragma unroll
+                for (int q = 0; q < R; ++q) lds[pb[q % P] + (q / P) * 17] = v[i * R + q];
             } else {
 #pragma unroll
                 for (int q = 0; q < R; ++q) lds[lds_pad(base + q * Ns)] = v[i * R + q];

@@ -922,12 +922,14 @@ hipError_t run_backward_t(const PlanData& d, int count, const void* G, const voi
 }
 
 // ----------------------------------------------------------------- batched
-// One image of a ragged batch: its sample offset in the packed buffer, its
-// shape, and the chirps of its forward and inverse chains.
-struct BatchImage {
+// One pass of one image of a ragged batch, built on the host: the pass
+// arguments (input and output pointers are taken from BatchArgs) and the
+// image's sample offset in the packed buffer.  Entry (img * 2 + dir) * 5 +
+// pass.
+template <typename T>
+struct BatchPass {
+    PassArgs<T> a;
     long long off;
-    int Nx, Ny;
-    ChirpArg turns[2][5];
 };
 struct BatchItem {
     int img;   // -1: padding item
@@ -937,7 +939,7 @@ template <typename T>
 struct BatchArgs {
     const cplx<T>* in;
     cplx<T>* out;
-    const BatchImage* imgs;
+    const BatchPass<T>* passes;
     const BatchItem* items;
     int nitems;
     int dir;
@@ -980,15 +982,21 @@ int host_batch_lines(int n) {
 // i mod 8, which is also the XCD of every workgroup that visits it (grid
 // size a multiple of 8).
 template <typename T, int N, bool COL>
-__global__ void __launch_bounds__(kBatchThreads) nslct_batched_pass(BatchArgs<T> b) {
+__global__ void __launch_bounds__(kBatchThreads)
+    nslct_batched_pass(BatchArgs<T> b, const BatchItem* __restrict__ items, const BatchPass<T>* __restrict__ passes) {
     constexpr int L = batch_lines<N>();
     __shared__ cplx<T> lds[L * lds_line_elems<N>()];
+    // The work list and the pass table come in as restrict parameters (no
+    // store of the kernel can alias them), so their uniform-index loads are
+    // scalar and the pass arguments stay in scalar registers.
     for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
-        const BatchItem w = b.items[it];
+        const BatchItem w = items[it];
         if (w.img >= 0) {
-            const BatchImage& im = b.imgs[w.img];
-            const PassArgs<T> a = make_pass_args<T>(im.Nx, im.Ny, im.turns[b.dir], b.pass, b.in, b.out);
-            pass_body<T, N, COL, L>(a, w.tile, (size_t)im.off, lds);
+            const int k = (w.img * 2 + b.dir) * 5 + b.pass;
+            PassArgs<T> a = passes[k].a;
+            a.in = b.in;
+            a.out = b.out;
+            pass_body<T, N, COL, L>(a, w.tile, (size_t)passes[k].off, lds);
         }
         __syncthreads();
     }
@@ -999,7 +1007,7 @@ hipError_t launch_batched_group(int N, const BatchArgs<T>& a, int grid, hipStrea
     switch (N) {
 #define NSLCT_CASE_LAUNCH(v)                                                                        \
     case v:                                                                                         \
-        hipLaunchKernelGGL((nslct_batched_pass<T, v, COL>), dim3(grid), dim3(kBatchThreads), 0, s, a); \
+        hipLaunchKernelGGL((nslct_batched_pass<T, v, COL>), dim3(grid), dim3(kBatchThreads), 0, s, a, a.items, a.passes); \
         return hipGetLastError();
         NSLCT_BATCH_SIZES(NSLCT_CASE_LAUNCH)
 #undef NSLCT_CASE_LAUNCH
@@ -1386,7 +1394,7 @@ struct nslct_batch_s {
     size_t total = 0;                 // samples in the packed buffer
     std::vector<long long> offsets;
     std::vector<nslct_plan_s> plans;  // copies of the input plans
-    BatchImage* d_imgs = nullptr;
+    void* d_passes = nullptr;  // BatchPass<T>[count * 10], T by precision
     // Work groups: one per (pass kind, line length).  Row passes ([0]) take
     // lines of length Ny, column passes ([1]) lines of length Nx.
     struct Group {
@@ -1415,7 +1423,7 @@ struct nslct_batch_s {
         for (auto e : ev) (void)hipEventDestroy(e);
         for (auto st : side) (void)hipStreamDestroy(st);
         if (cap) (void)hipStreamDestroy(cap);
-        if (d_imgs) (void)hipFree(d_imgs);
+        if (d_passes) (void)hipFree(d_passes);
         for (auto& gs : groups)
             for (auto& g : gs)
                 if (g.items) (void)hipFree(g.items);
@@ -1441,7 +1449,7 @@ hipError_t run_batched_t(const nslct_batch_s& b, int dir, const void* in, void* 
             BatchArgs<T> a;
             a.in = (const cplx<T>*)(pass == 0 ? in : out);
             a.out = (cplx<T>*)out;
-            a.imgs = b.d_imgs;
+            a.passes = (const BatchPass<T>*)b.d_passes;
             a.items = gs[k].items;
             a.nitems = gs[k].nitems;
             a.dir = dir;
@@ -1511,6 +1519,27 @@ void set_grids(nslct_batch_s* b, int mult, int cus) {
 int batch_fail(nslct_batch_s* b, hipError_t e, const char* what) {
     delete b;
     return fail(NSLCT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Builds and uploads the per-(image, direction, pass) argument table.
+template <typename T>
+hipError_t upload_batch_passes(nslct_batch_s& b) {
+    std::vector<BatchPass<T>> tab((size_t)b.count * 10);
+    for (int i = 0; i < b.count; ++i) {
+        const PlanData& d = b.plans[i].d;
+        for (int dir = 0; dir < 2; ++dir) {
+            ChirpArg c[5];
+            chain_args(d, dir, c);
+            for (int pass = 0; pass < 5; ++pass) {
+                BatchPass<T>& e = tab[((size_t)i * 2 + dir) * 5 + pass];
+                e.a = make_pass_args<T>(d.Nx, d.Ny, c, pass, nullptr, nullptr);
+                e.off = b.offsets[i];
+            }
+        }
+    }
+    hipError_t e = hipMalloc(&b.d_passes, sizeof(BatchPass<T>) * tab.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(b.d_passes, tab.data(), sizeof(BatchPass<T>) * tab.size(), hipMemcpyHostToDevice);
 }
 
 }  // namespace
@@ -1670,18 +1699,8 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
     }
     hipError_t e = hipGetDevice(&b->device);
     if (e != hipSuccess) return batch_fail(b, e, "hipGetDevice");
-    std::vector<BatchImage> imgs(count);
-    for (int i = 0; i < count; ++i) {
-        const PlanData& d = b->plans[i].d;
-        imgs[i].off = b->offsets[i];
-        imgs[i].Nx = d.Nx;
-        imgs[i].Ny = d.Ny;
-        for (int dir = 0; dir < 2; ++dir) chain_args(d, dir, imgs[i].turns[dir]);
-    }
-    e = hipMalloc(&b->d_imgs, sizeof(BatchImage) * count);
-    if (e != hipSuccess) return batch_fail(b, e, "hipMalloc");
-    e = hipMemcpy(b->d_imgs, imgs.data(), sizeof(BatchImage) * count, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return batch_fail(b, e, "hipMemcpy");
+    e = b->precision == NSLCT_C128 ? upload_batch_passes<double>(*b) : upload_batch_passes<float>(*b);
+    if (e != hipSuccess) return batch_fail(b, e, "pass table upload");
     for (int col = 0; col < 2; ++col) {
         std::vector<int> sizes;
         for (int i = 0; i < count; ++i) {
