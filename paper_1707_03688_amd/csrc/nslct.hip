@@ -977,11 +977,13 @@ int host_batch_lines(int n) {
     }
 }
 
-// Persistent batched pass over the images of one line length N: workgroups
-// walk the group's item list with a grid stride.  Item i belongs to XCD
-// i mod 8, which is also the XCD of every workgroup that visits it (grid
-// size a multiple of 8).
-template <typename T, int N, bool COL>
+// Batched pass over the images of one line length N.  LOOP: a persistent
+// grid whose workgroups walk the group's item list with a grid stride (item
+// i belongs to XCD i mod 8, which is also the XCD of every workgroup that
+// visits it: the grid size is a multiple of 8); otherwise one workgroup per
+// item, without the loop, whose loop-invariant values would otherwise stay
+// in registers across iterations.
+template <typename T, int N, bool COL, bool LOOP>
 __global__ void __launch_bounds__(kBatchThreads)
     nslct_batched_pass(BatchArgs<T> b, const BatchItem* __restrict__ items, const BatchPass<T>* __restrict__ passes) {
     constexpr int L = batch_lines<N>();
@@ -989,7 +991,7 @@ __global__ void __launch_bounds__(kBatchThreads)
     // The work list and the pass table come in as restrict parameters (no
     // store of the kernel can alias them), so their uniform-index loads are
     // scalar and the pass arguments stay in scalar registers.
-    for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+    auto item = [&](int it) {
         const BatchItem w = items[it];
         if (w.img >= 0) {
             const int k = (w.img * 2 + b.dir) * 5 + b.pass;
@@ -998,7 +1000,14 @@ __global__ void __launch_bounds__(kBatchThreads)
             a.out = b.out;
             pass_body<T, N, COL, L>(a, w.tile, (size_t)passes[k].off, lds);
         }
-        __syncthreads();
+    };
+    if constexpr (LOOP) {
+        for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+            item(it);
+            __syncthreads();
+        }
+    } else {
+        if ((int)blockIdx.x < b.nitems) item(blockIdx.x);
     }
 }
 
@@ -1007,7 +1016,12 @@ hipError_t launch_batched_group(int N, const BatchArgs<T>& a, int grid, hipStrea
     switch (N) {
 #define NSLCT_CASE_LAUNCH(v)                                                                        \
     case v:                                                                                         \
-        hipLaunchKernelGGL((nslct_batched_pass<T, v, COL>), dim3(grid), dim3(kBatchThreads), 0, s, a, a.items, a.passes); \
+        if (grid >= a.nitems)                                                                       \
+            hipLaunchKernelGGL((nslct_batched_pass<T, v, COL, false>), dim3(a.nitems), dim3(kBatchThreads), 0, s, a, \
+                               a.items, a.passes);                                                  \
+        else                                                                                        \
+            hipLaunchKernelGGL((nslct_batched_pass<T, v, COL, true>), dim3(grid), dim3(kBatchThreads), 0, s, a, \
+                               a.items, a.passes);                                                  \
         return hipGetLastError();
         NSLCT_BATCH_SIZES(NSLCT_CASE_LAUNCH)
 #undef NSLCT_CASE_LAUNCH
