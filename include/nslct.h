@@ -171,16 +171,24 @@ int nslct_plan_passes(nslct_plan_t plan, int* npasses);
  * off_0 = 0, images back to back in plan order.  All plans must share one
  * precision; sides must be 64, 128, 192, 256, 384, 512, 768 or 1024.  The
  * batch copies the plans (they may be destroyed afterwards), uploads a
- * per-image descriptor table and an XCD-balanced work list to the current
- * device, and autotunes the grid of its persistent pass kernels on scratch
- * images (device work and allocation happen here, once).  Not reentrant:
- * calls on one batch from several threads are serialised internally. */
+ * table of pass arguments per (image, direction, pass) and an XCD-balanced
+ * work list to the current device, and autotunes the grid of its pass
+ * kernels on scratch images (device work and allocation happen here, once).
+ * Not reentrant: calls on one batch from several threads are serialised
+ * internally. */
 int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out);
 
 /* Packed buffer length in samples, the autotuned persistent grid (workgroups
  * per CU; 0 = one workgroup per work item) and the forward time measured
  * while tuning, in microseconds (any pointer may be NULL). */
 int nslct_batch_info(nslct_batch_t batch, size_t* total_samples, int* mult, double* tuned_us);
+
+/* Overrides the autotuned grid: mult persistent workgroups per CU (1, 2, 4
+ * or 8) or 0 for one workgroup per work item; any other value is
+ * NSLCT_E_ARG.  Synchronises the batch's device, then drops the captured
+ * graphs (the next graph run captures again).  Results do not depend on the
+ * grid (each work item is computed by the same code whatever the grid). */
+int nslct_batch_set_grid(nslct_batch_t batch, int mult);
 
 /* Forward / inverse of every image of the batch: the five passes, each one
  * persistent launch per line length over all images of that length (the

@@ -212,6 +212,12 @@ class Batch:
     def inverse(self, x, out=None, stream=None):
         return self.run(x, out, 1, 0, stream)
 
+    def set_grid(self, mult: int):
+        """Override the autotuned grid (``nslct_batch_set_grid``): mult
+        workgroups per CU, or 0 for one workgroup per work item."""
+        check(lib.nslct_batch_set_grid(self._h, int(mult)))
+        self.mult = int(mult)
+
     def views(self, flat):
         """Per-image [Nx, Ny] views of a packed tensor."""
         return [flat[o:o + p.Nx * p.Ny].view(p.Nx, p.Ny) for o, p in zip(self.offsets, self.plans)]

@@ -1419,6 +1419,7 @@ struct nslct_batch_s {
     };
     std::vector<Group> groups[2];
     int mult = 0;  // autotuned persistent workgroups per CU (0: one per item)
+    int cus = 256;  // compute units of the device
     double tuned_us = 0.0;
     hipStream_t cap = nullptr;
     std::vector<hipStream_t> side;  // fork streams for concurrent groups
@@ -1751,6 +1752,7 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
     // Autotune the persistent grid (workgroups per CU) on scratch images.
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) cus = 256;
+    b->cus = cus;
     const size_t bytes = b->total * (b->precision == NSLCT_C128 ? 16 : 8);
     void* scratch = nullptr;
     e = hipMalloc(&scratch, bytes);
@@ -1792,6 +1794,23 @@ int nslct_batch_info(nslct_batch_t batch, size_t* total_samples, int* mult, doub
     if (total_samples) *total_samples = batch->total;
     if (mult) *mult = batch->mult;
     if (tuned_us) *tuned_us = batch->tuned_us;
+    return NSLCT_OK;
+}
+
+int nslct_batch_set_grid(nslct_batch_t batch, int mult) {
+    if (!batch) return fail(NSLCT_E_ARG, "null batch");
+    if (mult != 0 && mult != 1 && mult != 2 && mult != 4 && mult != 8)
+        return fail(NSLCT_E_ARG, "mult must be 0, 1, 2, 4 or 8");
+    std::lock_guard<std::mutex> lk(batch->mu);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && dev != batch->device) e = hipSetDevice(batch->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (dev >= 0 && dev != batch->device) (void)hipSetDevice(dev);
+    if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("set grid: ") + hipGetErrorString(e));
+    for (auto& g : batch->graphs) (void)hipGraphExecDestroy(g.exec);
+    batch->graphs.clear();
+    set_grids(batch, mult, batch->cus);
     return NSLCT_OK;
 }
 

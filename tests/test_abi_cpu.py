@@ -76,6 +76,8 @@ def test_error_codes(nl):
                                     None) == -1
     assert nl.lib.nslct_forward(None, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 20), None) == -1
     assert b"null" in nl.lib.nslct_last_error()
+    assert nl.lib.nslct_batch_set_grid(None, 0) == -1
+    assert nl.lib.nslct_batch_info(None, None, None, None) == -1
     assert nl.lib.nslct_strerror(-3) == b"no CM-CC-CM-CC decomposition"
 
 
