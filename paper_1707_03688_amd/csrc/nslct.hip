@@ -415,7 +415,11 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
     for (int sg = 0; sg < NS; ++sg) {
         cplx<T>* __restrict__ out = outs[sg];
         if constexpr (COL) {
-            __syncthreads();
+            // Before the first signal's staging each line's LDS region has
+            // only been used by that line's own threads, whose last DFT
+            // exchange ended with their sync; a second signal reuses regions
+            // the whole tile has just read.
+            if (sg > 0) __syncthreads();
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 const int p = pos(r);
