@@ -158,7 +158,8 @@ int nslct_inverse_many(nslct_plan_t plan, int count, const void* in, void* out, 
  * (direction 1) chain, pass = 0 .. nslct_plan_passes - 1, on `count` images:
  * pass 0 reads `in`, every pass writes `out`; chaining all passes with
  * in = out after the first equals nslct_forward_many / nslct_inverse_many.
- * For profiling. */
+ * A column pass over 4096-long columns (complex64 / complex128) is three
+ * kernel launches over 64 x 64 blocks of each column.  For profiling. */
 int nslct_launch_pass(nslct_plan_t plan, int direction, int pass, int count,
                       const void* in, void* out, void* stream);
 

@@ -462,8 +462,9 @@ constexpr int row_lines() {
 // Columns per tile: 4 (complex64) or 2 (complex128) adjacent columns, so a
 // row segment is 32 bytes, but no more than 512 threads per workgroup: a
 // 4096-long complex64 tile of 4 columns (1024 threads, 139 KB of LDS, one
-// workgroup per CU in lock step) measured 1.6x slower than 2 columns (two
-// independent workgroups per CU).
+// workgroup per CU in lock step) measured 1.6x slower than 2 columns.  (The
+// chain's 4096-long column passes run in three steps instead; these tiles
+// serve the reduced schedules and the other lengths.)
 template <typename T, int N>
 constexpr int col_lines() {
     constexpr int TPL = LinePlan<N>::TPL;

@@ -80,8 +80,8 @@ def test_forward_inverse_match_oracle_c64(torch, nl, shape, typ):
 def test_4096_long_columns_match_oracle(torch, nl, shape, precision):
     """Columns of length 4096 run as three launches over 64 x 64 blocks of 8
     columns (column counts that are and are not a multiple of 8): forward and
-    inverse against the oracle, in place, and three images in one call equal
-    to three calls.  complex128 runs at the spacing sqrt(2 pi / N): at 0.7 the
+    inverse against the oracle, in place, pass by pass, and three images in
+    one call equal to three calls.  complex128 runs at the spacing sqrt(2 pi / N): at 0.7 the
     chirp phases reach 1e6 rad, where the FP64 oracle's own phase rounding
     (one ulp of 1e6 is 1.2e-10) exceeds the 1e-11 bar."""
     Nx, Ny = shape
@@ -97,6 +97,10 @@ def test_4096_long_columns_match_oracle(torch, nl, shape, precision):
     y = x.clone()
     pg.forward(y, out=y)
     assert np.array_equal(y.cpu().numpy(), G)
+    z = torch.empty_like(x)
+    for p in range(5):
+        pg.launch_pass(0, p, x if p == 0 else z, z)
+    assert np.array_equal(z.cpu().numpy(), G)
     gs = np.stack([synth.complex_normal(shape, seed=Ny + k) for k in range(3)])
     Gb = pg.forward(_to_gpu(torch, gs, precision)).cpu().numpy()
     for k in range(3):
