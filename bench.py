@@ -31,7 +31,7 @@ HBM_PEAK_GBPS = 8000.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by the
 # copy-kernel calibration (profiles/nslct_pass_1024_c64_forward.md).  Set to
 # None whenever the kernels change until the counters are taken again.
-TRAFFIC_BYTES = {"rows": 16896 * 1024, "cols": 16926 * 1024}
+TRAFFIC_BYTES = {"rows": 16893 * 1024, "cols": 16925 * 1024}
 KERNEL_NAMES = {"rows": "nslct_pass<float, 1024, false, 4> (passes 0, 2, 4: row lines)",
                 "cols": "nslct_pass<float, 1024, true, 4> (passes 1, 3: column lines)"}
 
