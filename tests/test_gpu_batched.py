@@ -98,15 +98,17 @@ def test_batch_rejects_bad_input(torch, nl):
         nl.Batch([nl.Plan(M, 64, 64), nl.Plan(M, 64, 64, precision="c128")])
 
 
-def test_every_grid_mode_gives_the_same_bits(torch, nl):
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_every_grid_mode_gives_the_same_bits(torch, nl, precision):
     """The persistent grids (1, 2, 4, 8 workgroups per CU: the looping
     kernel) and one workgroup per item (the loop-free kernel) compute every
     item with the same code: graph replays in each mode equal the per-image
-    loop bitwise, forward and inverse; invalid modes are rejected."""
+    loop bitwise, forward and inverse, for complex64 (wide column tiles) and
+    complex128; invalid modes are rejected."""
     sizes = [1024, 768, 64, 384, 512, 128, 256, 192]
-    b, _ = _batch(nl, sizes, seed=47)
+    b, _ = _batch(nl, sizes, seed=47, precision=precision)
     g = synth.complex_normal((b.total,), seed=5)
-    x = torch.from_numpy(g).to(torch.complex64).cuda()
+    x = torch.from_numpy(g).to(torch.complex64 if precision == "c64" else torch.complex128).cuda()
     ref_f = b.run(x, mode=2)
     ref_i = b.run(x, direction=1, mode=2)
     for mult in (0, 1, 2, 4, 8):
