@@ -2,8 +2,8 @@
 
     python paper_1707_03688_amd/build.py        # or __graft_entry__.build()
 
-Every call recompiles.  Packed FP32 instructions are disabled for all device
-code (``-packed-fp32-ops``).
+Every call recompiles; the translation units compile in parallel.  Packed
+FP32 instructions are disabled for all device code (``-packed-fp32-ops``).
 """
 from __future__ import annotations
 
@@ -11,6 +11,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -48,17 +49,24 @@ def _run(cmd, verbose):
             print("\n".join(errs), flush=True)
 
 
+SOURCES = ("planner.cpp", "nslct.hip", "batched.hip", "split.hip", "backward.hip")
+
+
 def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     out_dir = os.path.join(PKG, "_build")
     os.makedirs(out_dir, exist_ok=True)
     inc = [f"-I{INCLUDE}", f"-I{CSRC}"]
-    objs = []
-    for src in ("planner.cpp", "nslct.hip"):
+    cmds, objs = [], []
+    for src in SOURCES:
         obj = os.path.join(out_dir, src.replace(".", "_") + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        _run([hipcc, *HIPCC_FLAGS, *inc, *lang, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        cmds.append([hipcc, *HIPCC_FLAGS, *inc, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([hipcc, *HIPCC_FLAGS, "-shared", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

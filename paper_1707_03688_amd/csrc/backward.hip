@@ -1,0 +1,113 @@
+// Backward sweep of the differentiable transform: the inverse chain run on
+// the forward output and on the incoming gradient together, with the
+// gradient sums of every chirp point, and the host steps that turn them into
+// dLoss / dtheta.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "internal.hpp"
+#include "pass_kernels.hpp"
+
+using namespace nslct;
+
+namespace {
+
+// Backward sweep: the inverse chain applied to the forward output G and to
+// the incoming gradient at once, with the gradient sums at every chirp point.
+template <typename T, int N, bool COL, int LINES>
+__global__ void __launch_bounds__(LinePlan<N>::TPL* LINES) nslct_pair_pass(PassArgs<T> a) {
+    __shared__ cplx<T> lds_all[LINES * lds_line_elems<N>()];
+    const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    pass_body<T, N, COL, LINES, 2>(a, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
+}
+
+#define NSLCT_PAIR_SIZES(X) X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+bool pair_size_ok(int n) {
+    switch (n) {
+#define NSLCT_PAIR_OK(v) case v:
+        NSLCT_PAIR_SIZES(NSLCT_PAIR_OK)
+#undef NSLCT_PAIR_OK
+        return true;
+        default:
+            return false;
+    }
+}
+
+template <typename T, bool COL>
+hipError_t launch_pair_n(int N, const PassArgs<T>& a, int count, hipStream_t s) {
+    switch (N) {
+#define NSLCT_PAIR_LAUNCH(v)                                                                     \
+    case v: {                                                                                    \
+        constexpr int L = COL ? col_lines<T, v>() : row_lines<T, v>();                           \
+        hipLaunchKernelGGL((nslct_pair_pass<T, v, COL, L>), dim3((a.nlines + L - 1) / L, count), \
+                           dim3(LinePlan<v>::TPL * L), 0, s, a);                                 \
+        return hipGetLastError();                                                                \
+    }
+        NSLCT_PAIR_SIZES(NSLCT_PAIR_LAUNCH)
+#undef NSLCT_PAIR_LAUNCH
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t run_backward_t(const PlanData& d, int count, const void* G, const void* gout, void* work, void* gx,
+                          double* sums, hipStream_t s) {
+    for (int pass = 0; pass < 5; ++pass) {
+        PassArgs<T> a = pass_args<T>(d, 1, pass, pass == 0 ? G : work, work);
+        a.in2 = (const cplx<T>*)(pass == 0 ? gout : gx);
+        a.out2 = (cplx<T>*)gx;
+        a.acc = sums + 3 * pass;
+        const bool col = (pass == 1 || pass == 3);
+        const hipError_t e = col ? launch_pair_n<T, true>(d.Nx, a, count, s) : launch_pair_n<T, false>(d.Ny, a, count, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+namespace nslct {
+hipError_t init_tables_backward() { return init_twiddles_here(); }
+}  // namespace nslct
+
+extern "C" {
+
+int nslct_backward(nslct_plan_t plan, int count, const void* G, const void* grad_out, void* work, void* grad_x,
+                   double* sums, void* stream) {
+    if (!plan) return fail(NSLCT_E_ARG, "null plan");
+    if (count < 1 || count > 65535) return fail(NSLCT_E_ARG, "count must be in [1, 65535]");
+    int rc = check_ptrs(G, grad_out);
+    if (!rc) rc = check_ptrs(work, grad_x);
+    if (rc) return rc;
+    if (!sums || ((uintptr_t)sums & 7)) return fail(NSLCT_E_ARG, "sums must be an 8-byte aligned device pointer");
+    const PlanData& d = plan->d;
+    if (d.precision != NSLCT_C64 && d.precision != NSLCT_C128)
+        return fail(NSLCT_E_UNSUPPORTED, "backward runs complex64 or complex128 plans");
+    if (!pair_size_ok(d.Nx) || !pair_size_ok(d.Ny))
+        return fail(NSLCT_E_SIZE, "backward sides must be 8..1024 (2^k) or 48, 96, 192, 384, 768");
+    if (work == grad_x || work == G || work == grad_out || grad_x == G)
+        return fail(NSLCT_E_ARG, "work and grad_x must be distinct from each other and from G");
+    rc = ensure_device_ready();
+    if (rc) return rc;
+    const hipError_t e = d.precision == NSLCT_C128
+                             ? run_backward_t<double>(d, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream)
+                             : run_backward_t<float>(d, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream);
+    return e == hipSuccess ? NSLCT_OK : fail(NSLCT_E_HIP, std::string("backward launch: ") + hipGetErrorString(e));
+}
+
+int nslct_plan_stage_gradient(nslct_plan_t plan, const double sums[15], double grad_stages[12]) {
+    if (!plan || !sums || !grad_stages) return fail(NSLCT_E_ARG, "null argument");
+    stage_gradient(plan->d, sums, grad_stages);
+    return NSLCT_OK;
+}
+
+int nslct_lie_point(const double abcd[16], const double theta[10], double out[16]) {
+    if (!abcd || !theta || !out) return fail(NSLCT_E_ARG, "null argument");
+    lie_point(abcd, theta, out);
+    return NSLCT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,497 @@
+// Ragged batches: many images, each with its own size and matrix, over one
+// packed buffer; per-(pass, line length) launches over XCD-balanced work
+// lists, captured in a HIP graph; autotuned at creation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <functional>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "pass_kernels.hpp"
+
+using namespace nslct;
+
+namespace {
+
+// One pass of one image of a ragged batch, built on the host: the pass
+// arguments (input and output pointers are taken from BatchArgs) and the
+// image's sample offset in the packed buffer.  Entry (img * 2 + dir) * 5 +
+// pass.
+template <typename T>
+struct BatchPass {
+    PassArgs<T> a;
+    long long off;
+};
+struct BatchItem {
+    int img;   // -1: padding item
+    int tile;  // line tile of that image
+};
+template <typename T>
+struct BatchArgs {
+    const cplx<T>* in;
+    cplx<T>* out;
+    const BatchPass<T>* passes;
+    const BatchItem* items;
+    int nitems;
+    int dir;
+    int pass;
+};
+
+constexpr int kBatchThreads = 256;
+// Line lengths the batched kernel handles (all with TPL <= 64).
+#define NSLCT_BATCH_SIZES(X) X(64) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+// Lines per work item: kBatchThreads threads' worth, doubled for complex64
+// column tiles (1024-long columns: 8 columns, 64-byte row segments; measured
+// 2.75 -> 2.68 ms on the 256-image ragged batch).
+template <int N, bool COL = false, typename T = float>
+constexpr int batch_lines() {
+    return ((COL && sizeof(T) == 4) ? 2 : 1) * kBatchThreads / LinePlan<N>::TPL;
+}
+bool batch_size_ok(int n) {
+    switch (n) {
+#define NSLCT_CASE_OK(v) case v:
+        NSLCT_BATCH_SIZES(NSLCT_CASE_OK)
+#undef NSLCT_CASE_OK
+        return true;
+        default:
+            return false;
+    }
+}
+
+int host_batch_lines(int n, bool col, bool dbl) {
+    switch (n) {
+#define NSLCT_CASE_L(v) \
+    case v:           \
+        return (col && !dbl) ? batch_lines<v, true, float>() : batch_lines<v>();
+        NSLCT_BATCH_SIZES(NSLCT_CASE_L)
+#undef NSLCT_CASE_L
+        default:
+            return 1;
+    }
+}
+
+// Batched pass over the images of one line length N.  LOOP: a persistent
+// grid whose workgroups walk the group's item list with a grid stride (item
+// i belongs to XCD i mod 8, which is also the XCD of every workgroup that
+// visits it: the grid size is a multiple of 8); otherwise one workgroup per
+// item, without the loop, whose loop-invariant values would otherwise stay
+// in registers across iterations.
+template <typename T, int N, bool COL, bool LOOP>
+__global__ void __launch_bounds__((batch_lines<N, COL, T>() * LinePlan<N>::TPL))
+    nslct_batched_pass(BatchArgs<T> b, const BatchItem* __restrict__ items, const BatchPass<T>* __restrict__ passes) {
+    constexpr int L = batch_lines<N, COL, T>();
+    __shared__ cplx<T> lds[L * lds_line_elems<N>()];
+    // The work list and the pass table come in as restrict parameters (no
+    // store of the kernel can alias them), so their uniform-index loads are
+    // scalar and the pass arguments stay in scalar registers.
+    auto item = [&](int it) {
+        const BatchItem w = items[it];
+        if (w.img >= 0) {
+            const int k = (w.img * 2 + b.dir) * 5 + b.pass;
+            PassArgs<T> a = passes[k].a;
+            a.in = b.in;
+            a.out = b.out;
+            pass_body<T, N, COL, L>(a, w.tile, (size_t)passes[k].off, lds);
+        }
+    };
+    if constexpr (LOOP) {
+        for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+            item(it);
+            __syncthreads();
+        }
+    } else {
+        if ((int)blockIdx.x < b.nitems) item(blockIdx.x);
+    }
+}
+
+template <typename T, bool COL>
+hipError_t launch_batched_group(int N, const BatchArgs<T>& a, int grid, hipStream_t s) {
+    switch (N) {
+#define NSLCT_CASE_LAUNCH(v)                                                                        \
+    case v:                                                                                         \
+        if (grid >= a.nitems)                                                                       \
+            hipLaunchKernelGGL((nslct_batched_pass<T, v, COL, false>), dim3(a.nitems),               \
+                               dim3(batch_lines<v, COL, T>() * LinePlan<v>::TPL), 0, s, a,          \
+                               a.items, a.passes);                                                  \
+        else                                                                                        \
+            hipLaunchKernelGGL((nslct_batched_pass<T, v, COL, true>), dim3(grid),                    \
+                               dim3(batch_lines<v, COL, T>() * LinePlan<v>::TPL), 0, s, a,          \
+                               a.items, a.passes);                                                  \
+        return hipGetLastError();
+        NSLCT_BATCH_SIZES(NSLCT_CASE_LAUNCH)
+#undef NSLCT_CASE_LAUNCH
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+
+}  // namespace
+
+struct nslct_batch_s {
+    int count = 0;
+    int precision = NSLCT_C64;
+    int device = 0;
+    size_t total = 0;                 // samples in the packed buffer
+    std::vector<long long> offsets;
+    std::vector<nslct_plan_s> plans;  // copies of the input plans
+    void* d_passes = nullptr;  // BatchPass<T>[count * 10], T by precision
+    // Work groups: one per (pass kind, line length).  Row passes ([0]) take
+    // lines of length Ny, column passes ([1]) lines of length Nx.
+    struct Group {
+        int N;
+        int nitems;
+        int grid;
+        BatchItem* items;
+    };
+    std::vector<Group> groups[2];
+    int mult = 0;  // autotuned persistent workgroups per CU (0: one per item)
+    int cus = 256;  // compute units of the device
+    double tuned_us = 0.0;
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> side;  // fork streams for concurrent groups
+    std::vector<hipEvent_t> ev;     // fork / join events
+    struct Graph {
+        const void* in;
+        void* out;
+        int dir;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    std::mutex mu;
+
+    ~nslct_batch_s() {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+        for (auto e : ev) (void)hipEventDestroy(e);
+        for (auto st : side) (void)hipStreamDestroy(st);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (d_passes) (void)hipFree(d_passes);
+        for (auto& gs : groups)
+            for (auto& g : gs)
+                if (g.items) (void)hipFree(g.items);
+    }
+};
+
+namespace {
+
+template <typename T>
+hipError_t run_batched_t(const nslct_batch_s& b, int dir, const void* in, void* out, hipStream_t s) {
+    for (int pass = 0; pass < 5; ++pass) {
+        const int col = (pass == 1 || pass == 3) ? 1 : 0;
+        const auto& gs = b.groups[col];
+        // Groups of one pass are independent: with fork streams they run
+        // concurrently (joined before the next pass).
+        const bool fork = gs.size() > 1 && b.side.size() >= gs.size();
+        hipError_t e = hipSuccess;
+        if (fork) {
+            e = hipEventRecord(b.ev[0], s);
+            for (size_t k = 0; k < gs.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(b.side[k], b.ev[0], 0);
+        }
+        for (size_t k = 0; k < gs.size() && e == hipSuccess; ++k) {
+            BatchArgs<T> a;
+            a.in = (const cplx<T>*)(pass == 0 ? in : out);
+            a.out = (cplx<T>*)out;
+            a.passes = (const BatchPass<T>*)b.d_passes;
+            a.items = gs[k].items;
+            a.nitems = gs[k].nitems;
+            a.dir = dir;
+            a.pass = pass;
+            hipStream_t st = fork ? b.side[k] : s;
+            e = col ? launch_batched_group<T, true>(gs[k].N, a, gs[k].grid, st)
+                    : launch_batched_group<T, false>(gs[k].N, a, gs[k].grid, st);
+            if (e == hipSuccess && fork) e = hipEventRecord(b.ev[1 + k], st);
+        }
+        if (fork)
+            for (size_t k = 0; k < gs.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, b.ev[1 + k], 0);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t run_batched(const nslct_batch_s& b, int dir, const void* in, void* out, hipStream_t s) {
+    return b.precision == NSLCT_C128 ? run_batched_t<double>(b, dir, in, out, s)
+                                     : run_batched_t<float>(b, dir, in, out, s);
+}
+
+// Work items of the images whose pass lines have length N, dealt to the 8
+// XCDs: whole images go to the least-loaded XCD (largest first), and item i
+// of the list belongs to XCD i mod 8, so adjacent line tiles of one image
+// share an XCD and its L2.
+std::vector<BatchItem> build_items(const nslct_batch_s& b, bool col, int N) {
+    std::vector<int> order;
+    for (int i = 0; i < b.count; ++i) {
+        const PlanData& d = b.plans[i].d;
+        if ((col ? d.Nx : d.Ny) == N) order.push_back(i);
+    }
+    auto cost = [&](int i) {
+        const PlanData& d = b.plans[i].d;
+        return (double)d.Nx * d.Ny;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    std::vector<std::vector<BatchItem>> per(8);
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int L = host_batch_lines(N, col, b.precision == NSLCT_C128);
+    for (int i : order) {
+        const PlanData& d = b.plans[i].d;
+        const int nl = col ? d.Ny : d.Nx;
+        const int tiles = (nl + L - 1) / L;
+        int x = 0;
+        for (int k = 1; k < 8; ++k)
+            if (load[k] < load[x]) x = k;
+        load[x] += cost(i);
+        for (int t = 0; t < tiles; ++t) per[x].push_back({i, t});
+    }
+    size_t len = 0;
+    for (auto& v : per) len = std::max(len, v.size());
+    std::vector<BatchItem> items(8 * len, BatchItem{-1, 0});
+    for (int x = 0; x < 8; ++x)
+        for (size_t k = 0; k < per[x].size(); ++k) items[8 * k + x] = per[x][k];
+    return items;
+}
+
+void set_grids(nslct_batch_s* b, int mult, int cus) {
+    b->mult = mult;
+    for (auto& gs : b->groups)
+        for (auto& g : gs) {
+            const int want = mult == 0 ? g.nitems : ((mult * cus + 7) / 8) * 8;
+            g.grid = std::max(8, std::min(want, g.nitems));
+        }
+}
+
+int batch_fail(nslct_batch_s* b, hipError_t e, const char* what) {
+    delete b;
+    return fail(NSLCT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Builds and uploads the per-(image, direction, pass) argument table.
+template <typename T>
+hipError_t upload_batch_passes(nslct_batch_s& b) {
+    std::vector<BatchPass<T>> tab((size_t)b.count * 10);
+    for (int i = 0; i < b.count; ++i) {
+        const PlanData& d = b.plans[i].d;
+        for (int dir = 0; dir < 2; ++dir) {
+            ChirpArg c[5];
+            chain_args(d, dir, c);
+            for (int pass = 0; pass < 5; ++pass) {
+                BatchPass<T>& e = tab[((size_t)i * 2 + dir) * 5 + pass];
+                e.a = make_pass_args<T>(d.Nx, d.Ny, c, pass, nullptr, nullptr);
+                e.off = b.offsets[i];
+            }
+        }
+    }
+    hipError_t e = hipMalloc(&b.d_passes, sizeof(BatchPass<T>) * tab.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(b.d_passes, tab.data(), sizeof(BatchPass<T>) * tab.size(), hipMemcpyHostToDevice);
+}
+
+
+}  // namespace
+
+namespace nslct {
+hipError_t init_tables_batched() { return init_twiddles_here(); }
+}  // namespace nslct
+
+extern "C" {
+
+int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out) {
+    if (!plans || !out || count < 1) return fail(NSLCT_E_ARG, "need plans, count >= 1 and out");
+    *out = nullptr;
+    auto* b = new (std::nothrow) nslct_batch_s;
+    if (!b) return fail(NSLCT_E_ARG, "out of host memory");
+    b->count = count;
+    b->precision = plans[0] ? plans[0]->d.precision : NSLCT_C64;
+    b->plans.resize(count);
+    b->offsets.resize(count);
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i]) {
+            delete b;
+            return fail(NSLCT_E_ARG, "null plan in batch");
+        }
+        const PlanData& d = plans[i]->d;
+        if (d.precision != b->precision) {
+            delete b;
+            return fail(NSLCT_E_ARG, "all plans of a batch must share one precision");
+        }
+        if (d.precision != NSLCT_C64 && d.precision != NSLCT_C128) {
+            delete b;
+            return fail(NSLCT_E_UNSUPPORTED, "batches run complex64 or complex128 plans");
+        }
+        if (!batch_size_ok(d.Nx) || !batch_size_ok(d.Ny)) {
+            delete b;
+            return fail(NSLCT_E_SIZE, "batched sides must be one of 64, 128, 192, 256, 384, 512, 768, 1024");
+        }
+        b->plans[i].d = d;
+        b->offsets[i] = (long long)b->total;
+        b->total += (size_t)d.Nx * d.Ny;
+    }
+    int rc = ensure_device_ready();
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) return batch_fail(b, e, "hipGetDevice");
+    e = b->precision == NSLCT_C128 ? upload_batch_passes<double>(*b) : upload_batch_passes<float>(*b);
+    if (e != hipSuccess) return batch_fail(b, e, "pass table upload");
+    for (int col = 0; col < 2; ++col) {
+        std::vector<int> sizes;
+        for (int i = 0; i < count; ++i) {
+            const int N = col ? b->plans[i].d.Nx : b->plans[i].d.Ny;
+            if (std::find(sizes.begin(), sizes.end(), N) == sizes.end()) sizes.push_back(N);
+        }
+        std::sort(sizes.begin(), sizes.end(), std::greater<int>());
+        for (int N : sizes) {
+            const std::vector<BatchItem> items = build_items(*b, col == 1, N);
+            nslct_batch_s::Group g{N, (int)items.size(), 8, nullptr};
+            e = hipMalloc(&g.items, sizeof(BatchItem) * items.size());
+            if (e != hipSuccess) return batch_fail(b, e, "hipMalloc");
+            b->groups[col].push_back(g);
+            e = hipMemcpy(g.items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return batch_fail(b, e, "hipMemcpy");
+        }
+    }
+    e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return batch_fail(b, e, "hipStreamCreate");
+    const size_t nside = std::max(b->groups[0].size(), b->groups[1].size());
+    for (size_t k = 0; k < nside && nside > 1; ++k) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) return batch_fail(b, e, "hipStreamCreate");
+        b->side.push_back(st);
+    }
+    for (size_t k = 0; k < nside + 1 && nside > 1; ++k) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return batch_fail(b, e, "hipEventCreate");
+        b->ev.push_back(ev);
+    }
+
+    // Autotune the persistent grid (workgroups per CU) on scratch images.
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) cus = 256;
+    b->cus = cus;
+    const size_t bytes = b->total * (b->precision == NSLCT_C128 ? 16 : 8);
+    void* scratch = nullptr;
+    e = hipMalloc(&scratch, bytes);
+    if (e != hipSuccess) return batch_fail(b, e, "hipMalloc (autotune scratch)");
+    e = hipMemsetAsync(scratch, 0, bytes, b->cap);
+    const int mults[] = {0, 1, 2, 4, 8};  // 0: one workgroup per item
+    double best = 1e30;
+    int best_mult = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int m : mults) {
+        if (e != hipSuccess) break;
+        set_grids(b, m, cus);
+        e = run_batched(*b, 0, scratch, scratch, b->cap);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, b->cap);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run_batched(*b, 0, scratch, scratch, b->cap);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->cap);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms / 3 * 1e3 < best) {
+            best = ms / 3 * 1e3;
+            best_mult = m;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) return batch_fail(b, e, "autotune");
+    set_grids(b, best_mult, cus);
+    b->tuned_us = best;
+    *out = b;
+    return NSLCT_OK;
+}
+
+int nslct_batch_info(nslct_batch_t batch, size_t* total_samples, int* mult, double* tuned_us) {
+    if (!batch) return fail(NSLCT_E_ARG, "null batch");
+    if (total_samples) *total_samples = batch->total;
+    if (mult) *mult = batch->mult;
+    if (tuned_us) *tuned_us = batch->tuned_us;
+    return NSLCT_OK;
+}
+
+int nslct_batch_set_grid(nslct_batch_t batch, int mult) {
+    if (!batch) return fail(NSLCT_E_ARG, "null batch");
+    if (mult != 0 && mult != 1 && mult != 2 && mult != 4 && mult != 8)
+        return fail(NSLCT_E_ARG, "mult must be 0, 1, 2, 4 or 8");
+    std::lock_guard<std::mutex> lk(batch->mu);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && dev != batch->device) e = hipSetDevice(batch->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (dev >= 0 && dev != batch->device) (void)hipSetDevice(dev);
+    if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("set grid: ") + hipGetErrorString(e));
+    for (auto& g : batch->graphs) (void)hipGraphExecDestroy(g.exec);
+    batch->graphs.clear();
+    set_grids(batch, mult, batch->cus);
+    return NSLCT_OK;
+}
+
+int nslct_batch_run(nslct_batch_t batch, int direction, int mode, const void* in, void* out, void* stream) {
+    if (!batch) return fail(NSLCT_E_ARG, "null batch");
+    if (direction != 0 && direction != 1) return fail(NSLCT_E_ARG, "direction must be 0 or 1");
+    if (mode < 0 || mode > 2) return fail(NSLCT_E_ARG, "mode must be 0, 1 or 2");
+    int rc = check_ptrs(in, out);
+    if (rc) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != batch->device) return fail(NSLCT_E_ARG, "batch used on another device than it was created on");
+    hipStream_t s = (hipStream_t)stream;
+    if (mode == 2) {  // per-image loop, one chain of launches per image
+        const size_t es = batch->precision == NSLCT_C128 ? 16 : 8;
+        for (int i = 0; i < batch->count; ++i) {
+            const char* pi = (const char*)in + batch->offsets[i] * es;
+            char* po = (char*)out + batch->offsets[i] * es;
+            rc = run_chain(&batch->plans[i], direction, 1, pi, po, stream);
+            if (rc) return rc;
+        }
+        return NSLCT_OK;
+    }
+    if (mode == 1) {
+        const hipError_t e = run_batched(*batch, direction, in, out, s);
+        return e == hipSuccess ? NSLCT_OK : fail(NSLCT_E_HIP, std::string("batched launch: ") + hipGetErrorString(e));
+    }
+    std::lock_guard<std::mutex> lk(batch->mu);
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : batch->graphs)
+        if (g.in == in && g.out == out && g.dir == direction) exec = g.exec;
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(batch->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t le = run_batched(*batch, direction, in, out, batch->cap);
+            e = hipStreamEndCapture(batch->cap, &graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        if (batch->graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(batch->graphs.front().exec);
+            batch->graphs.erase(batch->graphs.begin());
+        }
+        batch->graphs.push_back({in, out, direction, exec});
+    }
+    const hipError_t e = hipGraphLaunch(exec, s);
+    return e == hipSuccess ? NSLCT_OK : fail(NSLCT_E_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+}
+
+int nslct_forward_batched(nslct_batch_t batch, const void* in, void* out, void* stream) {
+    return nslct_batch_run(batch, 0, 0, in, out, stream);
+}
+
+int nslct_inverse_batched(nslct_batch_t batch, const void* in, void* out, void* stream) {
+    return nslct_batch_run(batch, 1, 0, in, out, stream);
+}
+
+void nslct_batch_destroy(nslct_batch_t batch) { delete batch; }
+
+}  // extern "C"

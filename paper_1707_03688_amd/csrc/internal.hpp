@@ -1,0 +1,39 @@
+// Host-side declarations shared by the library's translation units (not part
+// of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "nslct.h"
+#include "planner.hpp"
+
+struct nslct_plan_s {
+    nslct::PlanData d;
+};
+
+namespace nslct {
+
+// Records `msg` as this thread's last error and returns `code`.
+int fail(int code, const std::string& msg);
+
+// One-time per-device setup of every translation unit's device tables.
+int ensure_device_ready();
+
+// NSLCT_E_ARG unless both image pointers are non-null and 16-byte aligned.
+int check_ptrs(const void* in, const void* out);
+
+// The passes of one plan (forward dir 0, inverse dir 1) on `count` images.
+int run_chain(nslct_plan_t plan, int dir, int count, const void* in, void* out, void* stream);
+
+// Per translation unit: fill its device tables on the current device.
+hipError_t init_tables_batched();
+hipError_t init_tables_split();
+hipError_t init_tables_backward();
+
+// Pass `pass` (0..4) of a split-precision plan.
+hipError_t launch_split_pass(const PlanData& d, int dir, int pass, int count, const void* in, void* out,
+                             hipStream_t s);
+
+}  // namespace nslct
