@@ -253,9 +253,9 @@ def bench_backward(nl, torch, synth, np, count=32, N=512, reps=10):
     rng = np.random.default_rng(4)
     theta_star = rng.normal(0.0, 0.05, size=10)
     x = torch.from_numpy(synth.complex_normal((count, N, N), seed=4)).to(torch.complex64).cuda()
-    pstar = nl.Plan(ag.lie_point(M0, theta_star), N, N, d, d, symplectic_tol=1e-8)
+    pstar = nl.Plan.lie(M0, theta_star, N, N, d, d, symplectic_tol=1e-8)
     y = pstar.forward(x)
-    p0 = nl.Plan(M0, N, N, d, d, symplectic_tol=1e-8)
+    p0 = nl.Plan.lie(M0, np.zeros(10), N, N, d, d, symplectic_tol=1e-8)
     G = p0.forward(x)
     gout = 2 * (G - y)
     stream = torch.cuda.current_stream()

@@ -91,6 +91,8 @@ typedef struct {
                               5: LC-NsDLCT with H = (0,0;0,h) (eq. LC10),
                               6: LC-NsDLCT, the form with the smaller eq. HA24 objective */
     double symplectic_tol; /* accepted max|M J M^T - J|, default 1e-9 */
+    double det_min;        /* a middle CC matrix B' is accepted when |det B'| >= det_min * max(1, max|B_ij|^2)
+                              (the invertibility conditions of eqs. Bsym08 and Bnonsym32), default 1e-6 */
 } nslct_opts;
 
 /* Stage description of a plan (and input of nslct_plan_from_stages).
@@ -126,6 +128,18 @@ void nslct_opts_default(nslct_opts* opts);
 int nslct_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, nslct_plan_t* out);
 int nslct_plan_ex(const double abcd[16], int Nx, int Ny, double dx, double dy,
                   const nslct_opts* opts, nslct_plan_t* out);
+
+/* Plans M = M0 expm(J S(theta)) for differentiation (Sec. 6.2 with the
+ * parameterisation of the configs: theta holds the 10 coordinates of the Lie
+ * algebra of the ABCD group, the upper triangle, row by row, of the symmetric
+ * 4x4 S; J S is a general element of that algebra, so M satisfies eq. Intro12
+ * whenever M0 does).  The plan records (M0, theta) for nslct_backward_theta.
+ * With type_override 0 the type follows the trace rule (eq. Reversible08)
+ * even when B is symmetric: the CM-CC-CM form does not exist at perturbed
+ * matrices, so a differentiable plan keeps the CM-CC-CM-CC / CC-CM-CC-CM
+ * form.  Other options as nslct_plan_ex; host only. */
+int nslct_plan_lie(const double abcd0[16], const double theta[10], int Nx, int Ny, double dx, double dy,
+                   const nslct_opts* opts, nslct_plan_t* out);
 
 /* Plans from explicit stage matrices (type and mats read from *st; dx, dy
  * read from *st; other fields ignored).  Used to run the chain at fixed
@@ -216,6 +230,33 @@ void nslct_batch_destroy(nslct_batch_t batch);
  * Sides 8..1024 (2^k) or 48, 96, 192, 384, 768; work, grad_x distinct buffers. */
 int nslct_backward(nslct_plan_t plan, int count, const void* G, const void* grad_out, void* work, void* grad_x,
                    double* sums, void* stream);
+
+/* Gradients of a real loss of G = forward(x) with respect to x and to the
+ * plan's 10 Lie coordinates theta (plans from nslct_plan_lie, or nslct_plan /
+ * nslct_plan_ex, whose theta is 0 around M itself):
+ *   grad_x     = L^H grad_out = dLoss/dx (device, `count` images; L is
+ *                unitary, Sec. 6.2, and L^H is the inverse chain, eq.
+ *                CCCMCCCM30),
+ *   grad_theta = dLoss/dtheta (host, 10 doubles; may be NULL),
+ * where G is the forward output and grad_out = dLoss/dRe(G) + j dLoss/dIm(G)
+ * (device, `count` images each).  The sweep of nslct_backward runs on a work
+ * image and 15 sums that the library allocates on `stream`
+ * (hipMallocAsync) and frees after use; grad_theta chains the stage gradient
+ * (nslct_plan_stage_gradient) with d(stage entries)/d(theta)
+ * (nslct_plan_theta_jacobian) and the sum over images.  With grad_theta the
+ * call returns after `stream` has finished the sweep; without it the call is
+ * asynchronous.  grad_x must differ from G; sizes as nslct_backward.  Plans
+ * made from stage matrices have no theta: NSLCT_E_UNSUPPORTED when
+ * grad_theta is requested. */
+int nslct_backward_theta(nslct_plan_t plan, int count, const void* G, const void* grad_out, void* grad_x,
+                         double grad_theta[10], void* stream);
+
+/* Host: d(stage entries)/d(theta) of the plan at its own (M0, theta),
+ * jac[12][10] row-major (entries in the order of nslct_stages.mats), the
+ * planner differentiated as nslct_plan_jacobian does with its step chosen by
+ * the decomposition type (1e-4 for a searched gauge, 1e-5 for closed-form
+ * stages).  Computed once per plan and kept. */
+int nslct_plan_theta_jacobian(nslct_plan_t plan, double jac[12 * 10]);
 
 /* Host: the 15 sums of nslct_backward -> dLoss / d(stage-matrix entries),
  * 12 doubles in the order of nslct_stages.mats (x11, x12, x22 each).  The

@@ -57,6 +57,26 @@ class Plan:
         self.Nx, self.Ny = int(Nx), int(Ny)
 
     @classmethod
+    def lie(cls, M0, theta, Nx: int, Ny: int, dx: float = 1.0, dy: float = 1.0, precision: str = "c64",
+            type_override: int = 0, symplectic_tol: float = 1e-9) -> "Plan":
+        """Plan of M0 expm(J S(theta)) for differentiation (``nslct_plan_lie``)."""
+        opts = lib.opts()
+        opts.precision = _PRECISION[precision]
+        opts.type_override = int(type_override)
+        opts.symplectic_tol = float(symplectic_tol)
+        m = np.ascontiguousarray(np.asarray(M0, dtype=np.float64).reshape(16))
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(10))
+        h = ctypes.c_void_p()
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib.nslct_plan_lie(m.ctypes.data_as(dp), th.ctypes.data_as(dp), int(Nx), int(Ny), float(dx),
+                                 float(dy), ctypes.byref(opts), ctypes.byref(h)))
+        p = cls.__new__(cls)
+        p.precision = precision
+        p._h = h
+        p.Nx, p.Ny = int(Nx), int(Ny)
+        return p
+
+    @classmethod
     def from_stages(cls, typ: int, mats, Nx: int, Ny: int, dx: float, dy: float,
                     precision: str = "c64") -> "Plan":
         st = Stages()
@@ -139,6 +159,27 @@ class Plan:
 
     def inverse(self, x, out=None, stream=None):
         return self._run(lib.nslct_inverse_many, x, out, stream)
+
+    def backward_theta(self, G, grad_out, grad_x=None, want_theta: bool = True, stream=None):
+        """(grad_x, grad_theta) of ``nslct_backward_theta``: grad_x on the
+        device, grad_theta a numpy array of 10 doubles (None if not asked)."""
+        count = self._check_tensor(G)
+        self._check_tensor(grad_out)
+        if grad_x is None:
+            grad_x = _torch().empty_like(G)
+        self._check_tensor(grad_x)
+        gt = np.zeros(10) if want_theta else None
+        check(lib.nslct_backward_theta(self._h, int(count), ctypes.c_void_p(G.data_ptr()),
+                                       ctypes.c_void_p(grad_out.data_ptr()), ctypes.c_void_p(grad_x.data_ptr()),
+                                       gt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_theta else None,
+                                       ctypes.c_void_p(_stream_ptr(stream))))
+        return grad_x, gt
+
+    def theta_jacobian(self) -> np.ndarray:
+        """d(stage entries)/d(theta), shape (12, 10) (``nslct_plan_theta_jacobian``)."""
+        jac = np.zeros(120)
+        check(lib.nslct_plan_theta_jacobian(self._h, jac.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return jac.reshape(12, 10)
 
     def launch_pass(self, direction: int, pass_: int, x, out, stream=None):
         count = self._check_tensor(x)

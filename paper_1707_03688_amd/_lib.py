@@ -24,7 +24,7 @@ class NslctError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("type_override", ctypes.c_int),
-                ("symplectic_tol", ctypes.c_double)]
+                ("symplectic_tol", ctypes.c_double), ("det_min", ctypes.c_double)]
 
 
 class Stages(ctypes.Structure):
@@ -55,6 +55,8 @@ SIGNATURES = {
     "nslct_opts_default": (None, [ctypes.POINTER(Opts)]),
     "nslct_plan": (I, [ctypes.POINTER(D), I, I, D, D, ctypes.POINTER(P)]),
     "nslct_plan_ex": (I, [ctypes.POINTER(D), I, I, D, D, ctypes.POINTER(Opts), ctypes.POINTER(P)]),
+    "nslct_plan_lie": (I, [ctypes.POINTER(D), ctypes.POINTER(D), I, I, D, D, ctypes.POINTER(Opts),
+                           ctypes.POINTER(P)]),
     "nslct_plan_from_stages": (I, [ctypes.POINTER(Stages), I, I, ctypes.POINTER(Opts), ctypes.POINTER(P)]),
     "nslct_plan_get_stages": (I, [P, ctypes.POINTER(Stages)]),
     "nslct_plan_box_check": (I, [P, D, ctypes.POINTER(I)]),
@@ -74,6 +76,8 @@ SIGNATURES = {
     "nslct_batch_run": (I, [P, I, I, P, P, P]),
     "nslct_batch_destroy": (None, [P]),
     "nslct_backward": (I, [P, I, P, P, P, P, P, P]),
+    "nslct_backward_theta": (I, [P, I, P, P, P, ctypes.POINTER(D), P]),
+    "nslct_plan_theta_jacobian": (I, [P, ctypes.POINTER(D)]),
     "nslct_plan_stage_gradient": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
     "nslct_lie_point": (I, [ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),
     "nslct_plan_jacobian": (I, [ctypes.POINTER(D), ctypes.POINTER(D), I, I, D, D, ctypes.POINTER(Opts), D,

@@ -5,14 +5,12 @@ complex tensor [..., Nx, Ny] on the GPU) for the ABCD matrix
 M(theta) = M0 expm(J S(theta)), where theta holds the 10 coordinates of the
 Lie algebra of the ABCD group (the upper triangle of the symmetric 4x4 S).
 
-Backward (all in the library): ``nslct_backward`` runs the adjoint chain on
-the forward output and on the incoming gradient together (the transform is
-unitary, so dLoss/dx = L^H grad), and collects the derivative with respect to
-every stage-matrix entry at the chirp points; ``nslct_plan_stage_gradient``
-turns those sums into dLoss/d(stage entries) and ``nslct_plan_jacobian``
-gives d(stage entries)/d(theta) (planner at theta +- h, its gauge followed
-from the one at theta), whose
-product is dLoss/dtheta.  The binding only marshals arguments.
+Backward (all in the library): ``nslct_backward_theta`` runs the adjoint
+chain on the forward output and on the incoming gradient together (the
+transform is unitary, so dLoss/dx = L^H grad), collects the derivative with
+respect to every stage-matrix entry at the chirp points and chains it with
+d(stage entries)/d(theta) of the plan into dLoss/dtheta.  The binding only
+marshals arguments.
 """
 from __future__ import annotations
 
@@ -79,13 +77,10 @@ class NsLCTFunction(torch.autograd.Function):
     def forward(ctx, x, theta, M0, dx, dy, precision, type_override):
         th = theta.detach().to("cpu", torch.float64).numpy()
         Nx, Ny = int(x.shape[-2]), int(x.shape[-1])
-        M = lie_point(M0, th)
-        plan = Plan(M, Nx, Ny, dx, dy, precision=precision, type_override=type_override,
-                    symplectic_tol=1e-8)
+        plan = Plan.lie(M0, th, Nx, Ny, dx, dy, precision=precision, type_override=type_override,
+                        symplectic_tol=1e-8)
         G = plan.forward(x.contiguous())
         ctx.plan = plan
-        ctx.meta = (np.asarray(M0, dtype=np.float64), th, Nx, Ny, dx, dy, precision,
-                    plan.stages()["type"])
         ctx.theta_meta = (theta.dtype, theta.device)
         ctx.save_for_backward(G)
         return G
@@ -93,17 +88,10 @@ class NsLCTFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         (G,) = ctx.saved_tensors
-        plan = ctx.plan
-        grad_x, sums = backward_sums(plan, G, grad_out.contiguous())
-        M0, th, Nx, Ny, dx, dy, precision, typ = ctx.meta
-        gst = stage_gradient(plan, sums.cpu().numpy())
-        # Closed-form stages (types 3-5) take a smaller difference step than
-        # the searched HA gauge, whose minimiser is resolved to ~1e-12.
-        jac = plan_jacobian(M0, th, Nx, Ny, dx, dy, precision, type_override=typ,
-                            h=1e-5 if typ >= 3 else 1e-4)
-        gtheta = jac.T @ gst
+        grad_x, gtheta = ctx.plan.backward_theta(G, grad_out.contiguous(), want_theta=ctx.needs_input_grad[1])
         dtype, device = ctx.theta_meta
-        return grad_x, torch.as_tensor(gtheta, dtype=dtype, device=device), None, None, None, None, None
+        gt = torch.as_tensor(gtheta, dtype=dtype, device=device) if gtheta is not None else None
+        return grad_x, gt, None, None, None, None, None
 
 
 def nsdlct(x, theta, M0, dx: float, dy: float, precision: str = "c64", type_override: int = 0):

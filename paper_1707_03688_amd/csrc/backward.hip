@@ -4,6 +4,8 @@
 // dLoss / dtheta.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
 #include <string>
 
 #include "internal.hpp"
@@ -67,6 +69,66 @@ hipError_t run_backward_t(const PlanData& d, int count, const void* G, const voi
     return hipSuccess;
 }
 
+__global__ void zero_f64(double* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// Argument checks shared by the backward entry points.
+int check_backward(nslct_plan_t plan, int count, const void* G, const void* grad_out, const void* grad_x) {
+    if (!plan) return fail(NSLCT_E_ARG, "null plan");
+    if (count < 1 || count > 65535) return fail(NSLCT_E_ARG, "count must be in [1, 65535]");
+    int rc = check_ptrs(G, grad_out);
+    if (!rc) rc = check_ptrs(grad_x, grad_x);
+    if (rc) return rc;
+    const PlanData& d = plan->d;
+    if (d.precision != NSLCT_C64 && d.precision != NSLCT_C128)
+        return fail(NSLCT_E_UNSUPPORTED, "backward runs complex64 or complex128 plans");
+    if (!pair_size_ok(d.Nx) || !pair_size_ok(d.Ny))
+        return fail(NSLCT_E_SIZE, "backward sides must be 8..1024 (2^k) or 48, 96, 192, 384, 768");
+    if (grad_x == G) return fail(NSLCT_E_ARG, "grad_x must be distinct from G");
+    return NSLCT_OK;
+}
+
+// d(stage entries)/d(theta) of the plan, computed on first use.
+int plan_jac(nslct_plan_t plan, const double** jac) {
+    std::lock_guard<std::mutex> lk(plan->jac_mu);
+    if (!plan->jac_done) {
+        plan->jac_rc = plan_theta_jacobian(plan->d, plan->jac, &plan->jac_err);
+        plan->jac_done = true;
+    }
+    if (plan->jac_rc) return fail(plan->jac_rc, plan->jac_err);
+    *jac = plan->jac;
+    return NSLCT_OK;
+}
+
+// The paired sweep of `count` images through a work image region of `chunk`
+// images (work holds chunk images; the images are processed chunk by
+// chunk), accumulating into the device sums[15] (cleared here first).
+hipError_t sweep_chunks(const PlanData& d, int count, int chunk, const void* G, const void* gout, void* work,
+                        void* gx, double* sums, hipStream_t s) {
+    hipLaunchKernelGGL(zero_f64, dim3(1), dim3(64), 0, s, sums, 15);
+    hipError_t e = hipGetLastError();
+    const size_t es = d.precision == NSLCT_C128 ? 16 : 8;
+    const size_t img = (size_t)d.Nx * d.Ny * es;
+    for (int i0 = 0; e == hipSuccess && i0 < count; i0 += chunk) {
+        const int n = std::min(chunk, count - i0);
+        const char* g = (const char*)G + i0 * img;
+        const char* go = (const char*)gout + i0 * img;
+        char* x = (char*)gx + i0 * img;
+        e = d.precision == NSLCT_C128 ? run_backward_t<double>(d, n, g, go, work, x, sums, s)
+                                      : run_backward_t<float>(d, n, g, go, work, x, sums, s);
+    }
+    return e;
+}
+
+// Host part: the 15 sums -> dLoss/d(stage entries) -> dLoss/dtheta.
+void finish_theta(const PlanData& d, const double* jac, const double sums[15], double grad_theta[10]) {
+    double gst[12];
+    stage_gradient(d, sums, gst);
+    theta_gradient(jac, gst, grad_theta);
+}
+
 }  // namespace
 
 namespace nslct {
@@ -96,6 +158,46 @@ int nslct_backward(nslct_plan_t plan, int count, const void* G, const void* grad
                              ? run_backward_t<double>(d, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream)
                              : run_backward_t<float>(d, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream);
     return e == hipSuccess ? NSLCT_OK : fail(NSLCT_E_HIP, std::string("backward launch: ") + hipGetErrorString(e));
+}
+
+int nslct_backward_theta(nslct_plan_t plan, int count, const void* G, const void* grad_out, void* grad_x,
+                         double grad_theta[10], void* stream) {
+    int rc = check_backward(plan, count, G, grad_out, grad_x);
+    if (rc) return rc;
+    const PlanData& d = plan->d;
+    const double* jac = nullptr;
+    if (grad_theta) {
+        rc = plan_jac(plan, &jac);
+        if (rc) return rc;
+    }
+    rc = ensure_device_ready();
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t es = d.precision == NSLCT_C128 ? 16 : 8;
+    const size_t work_bytes = (size_t)count * d.Nx * d.Ny * es;
+    void* buf = nullptr;
+    hipError_t e = hipMallocAsync(&buf, work_bytes + 256, s);
+    if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("backward work image: ") + hipGetErrorString(e));
+    double* sums = (double*)buf;
+    void* work = (char*)buf + 256;
+    double host[15] = {};
+    e = sweep_chunks(d, count, count, G, grad_out, work, grad_x, sums, s);
+    if (e == hipSuccess && grad_theta) e = hipMemcpyAsync(host, sums, sizeof host, hipMemcpyDeviceToHost, s);
+    const hipError_t ef = hipFreeAsync(buf, s);
+    if (e == hipSuccess) e = ef;
+    if (e == hipSuccess && grad_theta) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("backward: ") + hipGetErrorString(e));
+    if (grad_theta) finish_theta(d, jac, host, grad_theta);
+    return NSLCT_OK;
+}
+
+int nslct_plan_theta_jacobian(nslct_plan_t plan, double jac[12 * 10]) {
+    if (!plan || !jac) return fail(NSLCT_E_ARG, "null argument");
+    const double* j = nullptr;
+    const int rc = plan_jac(plan, &j);
+    if (rc) return rc;
+    std::memcpy(jac, j, sizeof(double) * 120);
+    return NSLCT_OK;
 }
 
 int nslct_plan_stage_gradient(nslct_plan_t plan, const double sums[15], double grad_stages[12]) {

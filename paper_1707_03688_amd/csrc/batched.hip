@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -139,7 +140,7 @@ struct nslct_batch_s {
     int device = 0;
     size_t total = 0;                 // samples in the packed buffer
     std::vector<long long> offsets;
-    std::vector<nslct_plan_s> plans;  // copies of the input plans
+    std::unique_ptr<nslct_plan_s[]> plans;  // copies of the input plans
     void* d_passes = nullptr;  // BatchPass<T>[count * 10], T by precision
     // Work groups: one per (pass kind, line length).  Row passes ([0]) take
     // lines of length Ny, column passes ([1]) lines of length Nx.
@@ -305,7 +306,11 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
     if (!b) return fail(NSLCT_E_ARG, "out of host memory");
     b->count = count;
     b->precision = plans[0] ? plans[0]->d.precision : NSLCT_C64;
-    b->plans.resize(count);
+    b->plans.reset(new (std::nothrow) nslct_plan_s[count]);
+    if (!b->plans) {
+        delete b;
+        return fail(NSLCT_E_ARG, "out of host memory");
+    }
     b->offsets.resize(count);
     for (int i = 0; i < count; ++i) {
         if (!plans[i]) {
@@ -456,6 +461,8 @@ int nslct_batch_run(nslct_batch_t batch, int direction, int mode, const void* in
         return NSLCT_OK;
     }
     if (mode == 1) {
+        // The batch's fork streams and events are shared: one call at a time.
+        std::lock_guard<std::mutex> lk(batch->mu);
         const hipError_t e = run_batched(*batch, direction, in, out, s);
         return e == hipSuccess ? NSLCT_OK : fail(NSLCT_E_HIP, std::string("batched launch: ") + hipGetErrorString(e));
     }

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 
 #include "nslct.h"
@@ -11,6 +12,13 @@
 
 struct nslct_plan_s {
     nslct::PlanData d;
+    // d(stage entries)/d(theta), computed on the first backward call that
+    // needs it (the plan stays logically immutable).
+    std::mutex jac_mu;
+    bool jac_done = false;
+    int jac_rc = 0;
+    std::string jac_err;
+    double jac[12 * 10] = {};
 };
 
 namespace nslct {

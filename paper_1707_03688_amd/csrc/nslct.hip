@@ -657,6 +657,7 @@ void nslct_opts_default(nslct_opts* o) {
     o->precision = NSLCT_C64;
     o->type_override = 0;
     o->symplectic_tol = 1e-9;
+    o->det_min = 1e-6;
 }
 
 int nslct_plan_ex(const double abcd[16], int Nx, int Ny, double dx, double dy, const nslct_opts* opts,
@@ -670,6 +671,25 @@ int nslct_plan_ex(const double abcd[16], int Nx, int Ny, double dx, double dy, c
     if (!p) return fail(NSLCT_E_ARG, "out of host memory");
     std::string err;
     const int rc = build_plan(abcd, Nx, Ny, dx, dy, o, &p->d, &err);
+    if (rc) {
+        delete p;
+        return fail(rc, err);
+    }
+    *out = p;
+    return NSLCT_OK;
+}
+
+int nslct_plan_lie(const double abcd0[16], const double theta[10], int Nx, int Ny, double dx, double dy,
+                   const nslct_opts* opts, nslct_plan_t* out) {
+    if (!abcd0 || !theta || !out) return fail(NSLCT_E_ARG, "null argument");
+    *out = nullptr;
+    nslct_opts o;
+    nslct_opts_default(&o);
+    if (opts) o = *opts;
+    auto* p = new (std::nothrow) nslct_plan_s;
+    if (!p) return fail(NSLCT_E_ARG, "out of host memory");
+    std::string err;
+    const int rc = build_plan_lie(abcd0, theta, Nx, Ny, dx, dy, o, &p->d, &err);
     if (rc) {
         delete p;
         return fail(rc, err);

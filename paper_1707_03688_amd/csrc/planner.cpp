@@ -10,7 +10,8 @@
 //   4. Gauge: minimise the product of the growth ratios gamma (eq. HA16) of
 //      the four stage matrices (eq. HA24) over symmetric H with B' = B - A H
 //      symmetric (type 1, eq. Bnonsym32) or B1' = B - H1 D symmetric (type 2,
-//      eq. CCCMCCCM08), |det B'| >= 1e-6 max(1, max|B_ij|^2).  The feasible
+//      eq. CCCMCCCM08), |det B'| >= det_min max(1, max|B_ij|^2) (det_min
+//      an option, default 1e-6).  The feasible
 //      set is a plane (or all of Sym(2)); the objective is piecewise smooth
 //      with minima on |.| kinks, so the search is exhaustive on a grid, then
 //      Nelder-Mead, then Newton "snapping" onto the kinks.  Ties within
@@ -19,13 +20,17 @@
 //      eq. Bnonsym12; type 2: H1, Q1 = (D-I)B1'^-1, B1', Q3 = B1'^-1(A1'-I),
 //      eq. CCCMCCCM16), symmetrised, then the five-slot chain and its adjoint
 //      (eq. CCCMCCCM30) with phase coefficients in fixed-point turns.
-// Reduced decompositions on request (type_override 3..6):
+// Reduced decompositions:
 //   * CM-CC-CM when B is symmetric and invertible (Sec. 4.1, eqs. Bsym04-12):
-//     P1 = (D - I) B^-1, B, P3 = B^-1 (A - I).
-//   * LC-NsDLCT (Sec. 4.2.2, eqs. LC04-LC12): the type-1 form with the
-//     rank-one gauge H = (h, 0; 0, 0), h = (b21 - b12) / a21 (eq. LC08), or
-//     H = (0, 0; 0, h), h = (b12 - b21) / a12 (eq. LC10); with both available,
-//     the smaller eq. HA24 objective.
+//     P1 = (D - I) B^-1, B, P3 = B^-1 (A - I).  Chosen without an override
+//     when B = B^T and |det B| >= the det_min bound (the case split of
+//     Secs. 4.1 / 4.2), or on request (type_override 3).
+//   * LC-NsDLCT (Sec. 4.2.2, eqs. LC04-LC12), on request (type_override 4..6):
+//     the type-1 form with the rank-one gauge H = (h, 0; 0, 0),
+//     h = (b21 - b12) / a21 (eq. LC08), or H = (0, 0; 0, h),
+//     h = (b12 - b21) / a12 (eq. LC10); with both available, the smaller
+//     eq. HA24 objective (6); with neither giving an invertible B', option 6
+//     falls back to the HA-NsDLCT as the paper prescribes.
 //   Both are five-slot chains with zero slots, run as three passes.
 #include "planner.hpp"
 
@@ -645,6 +650,10 @@ int check_common(int Nx, int Ny, double dx, double dy, const nslct_opts& o, std:
         *err = "type_override must be in 0..6";
         return NSLCT_E_ARG;
     }
+    if (!(o.det_min > 0) || !std::isfinite(o.det_min)) {
+        *err = "det_min must be finite and positive";
+        return NSLCT_E_ARG;
+    }
     return NSLCT_OK;
 }
 
@@ -656,19 +665,52 @@ double gamma_ratio(const double x[3]) {
 
 namespace {
 int build_plan_from(const double abcd[16], int Nx, int Ny, double dx, double dy, const nslct_opts& o,
-                    PlanData* out, std::string* err, const double* start_gauge);
+                    PlanData* out, std::string* err, const double* start_gauge, bool auto_bsym);
 }  // namespace
 
 int build_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, const nslct_opts& o,
                PlanData* out, std::string* err) {
-    return build_plan_from(abcd, Nx, Ny, dx, dy, o, out, err, nullptr);
+    const int rc = build_plan_from(abcd, Nx, Ny, dx, dy, o, out, err, nullptr, true);
+    if (rc) return rc;
+    out->has_lie = 1;
+    std::memcpy(out->abcd0, abcd, sizeof out->abcd0);
+    std::memset(out->theta, 0, sizeof out->theta);
+    out->opts = o;
+    return NSLCT_OK;
+}
+
+// A plan that is to be differentiated keeps one decomposition type in a
+// neighbourhood of theta: the automatic choice of CM-CC-CM for a symmetric B
+// (which a perturbation of theta breaks) is not made, the trace rule picks
+// the CM-CC-CM-CC or CC-CM-CC-CM form instead.
+int build_plan_lie(const double abcd0[16], const double theta[10], int Nx, int Ny, double dx, double dy,
+                   const nslct_opts& o, PlanData* out, std::string* err) {
+    for (int i = 0; i < 16; ++i)
+        if (!std::isfinite(abcd0[i])) {
+            *err = "ABCD matrix has a non-finite entry";
+            return NSLCT_E_ARG;
+        }
+    for (int i = 0; i < 10; ++i)
+        if (!std::isfinite(theta[i])) {
+            *err = "theta has a non-finite entry";
+            return NSLCT_E_ARG;
+        }
+    double M[16];
+    lie_point(abcd0, theta, M);
+    const int rc = build_plan_from(M, Nx, Ny, dx, dy, o, out, err, nullptr, false);
+    if (rc) return rc;
+    out->has_lie = 1;
+    std::memcpy(out->abcd0, abcd0, sizeof out->abcd0);
+    std::memcpy(out->theta, theta, sizeof out->theta);
+    out->opts = o;
+    return NSLCT_OK;
 }
 
 namespace {
 // start_gauge: a gauge of a neighbouring matrix to follow locally (HA types
 // with type_override 1 or 2 only), else the full search.
 int build_plan_from(const double abcd[16], int Nx, int Ny, double dx, double dy, const nslct_opts& o,
-                    PlanData* out, std::string* err, const double* start_gauge) {
+                    PlanData* out, std::string* err, const double* start_gauge, bool auto_bsym) {
     int rc = check_common(Nx, Ny, dx, dy, o, err);
     if (rc) return rc;
     for (int i = 0; i < 16; ++i)
@@ -710,8 +752,15 @@ int build_plan_from(const double abcd[16], int Nx, int Ny, double dx, double dy,
         *err = "B = 0 with A or D != I is an affine map, not decomposable into CMs and CCs";
         return NSLCT_E_NO_DECOMPOSITION;
     }
-    const double dmin = 1e-6 * std::max(1.0, bmax * bmax);
-    if (o.type_override == 3) {  // CM-CC-CM (eq. Bsym08: B symmetric, invertible)
+    const double dmin = o.det_min * std::max(1.0, bmax * bmax);
+    // Sec. 4.1 covers B = B^T with det B != 0 (eq. Bsym08) by CM-CC-CM, Sec.
+    // 4.2 the other matrices by CM-CC-CM-CC: without an override a
+    // symmetric invertible B is planned as CM-CC-CM.  (CM-CC-CM is the type-1
+    // chain at the gauge H = 0, which is feasible exactly when B is symmetric.)
+    const bool bsym_auto = auto_bsym && o.type_override == 0 &&
+                           std::fabs(b.B.a12 - b.B.a21) <= 1e-12 * std::max(1.0, bmax) &&
+                           std::fabs(det(b.B)) >= dmin;
+    if (o.type_override == 3 || bsym_auto) {  // CM-CC-CM (eq. Bsym08: B symmetric, invertible)
         if (std::fabs(b.B.a12 - b.B.a21) > 1e-9 * std::max(1.0, bmax)) {
             *err = "CM-CC-CM needs a symmetric B (eq. Bsym08)";
             return NSLCT_E_NO_DECOMPOSITION;
@@ -750,25 +799,29 @@ int build_plan_from(const double abcd[16], int Nx, int Ny, double dx, double dy,
                 std::memcpy(bh, h, sizeof bh);
             }
         }
-        if (!btype) {
+        if (btype) {
+            double dt;
+            g.stages(bh, s.mats, &dt);
+            s.type = btype;
+            std::memcpy(s.h, bh, sizeof s.h);
+            s.gauge_objective = best;
+            fill_chains(out);
+            return NSLCT_OK;
+        }
+        if (o.type_override != 6) {
             *err = "no rank-one gauge with invertible B' (eqs. LC08, LC10)";
             return NSLCT_E_NO_DECOMPOSITION;
         }
-        double dt;
-        g.stages(bh, s.mats, &dt);
-        s.type = btype;
-        std::memcpy(s.h, bh, sizeof s.h);
-        s.gauge_objective = best;
-        fill_chains(out);
-        return NSLCT_OK;
+        // Neither rank-one form gives an invertible B': the HA-NsDLCT is used
+        // instead (Sec. 4.2.2), its type by the trace rule.
     }
-    int type = o.type_override;
+    int type = o.type_override >= 4 ? 0 : o.type_override;
     if (type == 0) type = (b.B.a11 + b.B.a22) < 0 ? 2 : 1;
     Gauge g{b, type, dmin};
     GaugeOut go;
     if (start_gauge && o.type_override != 0) go = solve(g, mmax, start_gauge);
     if (!go.found) go = solve(g, mmax);
-    if (o.type_override == 0 && !go.feasible) {
+    if ((o.type_override == 0 || o.type_override == 6) && !go.feasible) {
         g.type = type = 3 - type;
         go = solve(g, mmax);
     }
@@ -899,7 +952,7 @@ int plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny
     double M0[16];
     lie_point(abcd, theta0, M0);
     PlanData base;
-    int rc = build_plan(M0, Nx, Ny, dx, dy, o, &base, err);
+    int rc = build_plan_from(M0, Nx, Ny, dx, dy, o, &base, err, nullptr, false);
     if (rc) return rc;
     nslct_opts of = o;
     of.type_override = base.st.type == 0 ? 0 : base.st.type;  // stay on one decomposition type
@@ -911,8 +964,8 @@ int plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny
         lie_point(abcd, tp, Mp);
         lie_point(abcd, tm, Mm);
         PlanData pp, pm;
-        rc = build_plan_from(Mp, Nx, Ny, dx, dy, of, &pp, err, base.st.h);
-        if (!rc) rc = build_plan_from(Mm, Nx, Ny, dx, dy, of, &pm, err, base.st.h);
+        rc = build_plan_from(Mp, Nx, Ny, dx, dy, of, &pp, err, base.st.h, false);
+        if (!rc) rc = build_plan_from(Mm, Nx, Ny, dx, dy, of, &pm, err, base.st.h, false);
         if (rc) return rc;
         if (pp.st.type != pm.st.type) {
             *err = "decomposition type changes within the difference step";
@@ -922,6 +975,31 @@ int plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny
             for (int k = 0; k < 3; ++k) jac[(3 * m + k) * 10 + i] = (pp.st.mats[m][k] - pm.st.mats[m][k]) / (2 * h);
     }
     return NSLCT_OK;
+}
+
+int plan_theta_jacobian(const PlanData& p, double jac[12 * 10], std::string* err) {
+    if (!p.has_lie) {
+        *err = "the plan was made from stage matrices: no ABCD parameterisation to differentiate";
+        return NSLCT_E_UNSUPPORTED;
+    }
+    if (p.st.type == 3 && p.opts.type_override == 0) {
+        *err = "a CM-CC-CM plan chosen for a symmetric B has no decomposition of the same type at "
+               "perturbed matrices; plan with nslct_plan_lie to differentiate";
+        return NSLCT_E_UNSUPPORTED;
+    }
+    nslct_opts o = p.opts;
+    // Closed-form stages (types 3-5) take a smaller difference step than the
+    // searched gauge, whose minimiser is resolved to about 1e-12.
+    const double h = p.st.type >= 3 ? 1e-5 : 1e-4;
+    return plan_jacobian(p.abcd0, p.theta, p.Nx, p.Ny, p.st.dx, p.st.dy, o, h, jac, err);
+}
+
+void theta_gradient(const double jac[12 * 10], const double gst[12], double out[10]) {
+    for (int i = 0; i < 10; ++i) {
+        double acc = 0;
+        for (int m = 0; m < 12; ++m) acc += jac[m * 10 + i] * gst[m];
+        out[i] = acc;
+    }
 }
 
 void stage_gradient(const PlanData& p, const double sums[15], double g[12]) {

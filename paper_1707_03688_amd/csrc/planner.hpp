@@ -52,6 +52,13 @@ struct PlanData {
     int precision;
     Chain5 dir[2];     // [0] forward, [1] inverse (adjoint): five-slot form
     Program prog[2];   // reduced three-pass schedule of the same chain
+    // The planned matrix as M = M0 expm(J S(theta)) (theta = 0 for a plan of
+    // M itself) and the options it was planned with, for the derivative of
+    // the stage matrices along theta; has_lie = 0 for plans made from stages.
+    int has_lie;
+    double abcd0[16];
+    double theta[10];
+    nslct_opts opts;
 };
 
 // Symmetric 2x2 (x11, x12, x22) helpers exposed for tests of the planner.
@@ -62,14 +69,22 @@ int build_plan(const double abcd[16], int Nx, int Ny, double dx, double dy, cons
                PlanData* out, std::string* err);
 int build_plan_from_stages(const nslct_stages& st, int Nx, int Ny, const nslct_opts& o,
                            PlanData* out, std::string* err);
+// Plans M = M0 expm(J S(theta)) and records (M0, theta).
+int build_plan_lie(const double abcd0[16], const double theta[10], int Nx, int Ny, double dx, double dy,
+                   const nslct_opts& o, PlanData* out, std::string* err);
 // M expm(J S(theta)) (10 Lie coordinates theta).
 void lie_point(const double abcd[16], const double theta[10], double* M);
 // d(stage entries)/d(theta) at theta0 for M(theta) = M expm(J S(theta)),
 // central differences of the planner with step h.
 int plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny, double dx, double dy,
                   const nslct_opts& o, double h, double jac[12 * 10], std::string* err);
+// d(stage entries)/d(theta) of a plan at its own (M0, theta), with the
+// difference step of its decomposition type.
+int plan_theta_jacobian(const PlanData& p, double jac[12 * 10], std::string* err);
 // Raw backward sums (15) -> d loss / d(stage entries) (12, order of st.mats).
 void stage_gradient(const PlanData& p, const double sums[15], double g[12]);
+// d loss / d theta = jac^T (d loss / d stages).
+void theta_gradient(const double jac[12 * 10], const double gst[12], double out[10]);
 // Phase-space box check (eqs. HA12-HA20) with the input in fraction `frac`.
 bool box_check(const PlanData& p, double frac);
 

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import gauge as ogauge, plan as oplan, symplectic
+from oracle import fast, gauge as ogauge, plan as oplan, symplectic
 from oracle_fixtures import paper_matrices
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -108,13 +108,30 @@ def _draws():
     return out
 
 
+def _bsym(M):
+    B = M[:2, 2:]
+    bmax = max(1.0, float(np.max(np.abs(B))))
+    return abs(B[0, 1] - B[1, 0]) <= 1e-12 * bmax and abs(np.linalg.det(B)) >= 1e-6 * bmax ** 2
+
+
 def test_planner_agrees_with_oracle_gauge(nl):
-    """Same type; gauge objective equal to relative 1e-8 (two independent
-    searches of eq. HA24); planner stages multiply back to M (eq. Bnonsym08 /
+    """Without an override a symmetric invertible B is planned as CM-CC-CM
+    (the case split of Secs. 4.1 / 4.2) with the oracle's stages; otherwise,
+    and for every matrix under the trace-rule type, the same type as the
+    oracle; gauge objective equal to relative 1e-8 (two independent searches
+    of eq. HA24); planner stages multiply back to M (eq. Bnonsym08 /
     CCCMCCCM12) and the planner's H is feasible and optimal for the oracle's
     objective too."""
+    nsym = 0
     for M in _draws():
-        st = nl.Plan(M, 32, 32, 0.5, 0.5).stages()
+        if _bsym(M):
+            nsym += 1
+            st = nl.Plan(M, 32, 32, 0.5, 0.5).stages()
+            ref = fast.cmccm_plan(M, 32, 32, 0.5, 0.5)
+            assert st["type"] == 3
+            for a, b in zip(st["mats"][:3], ref.mats):
+                assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.max(np.abs(b)))
+        st = nl.Plan(M, 32, 32, 0.5, 0.5, type_override=ogauge.trace_type(M)).stages()
         po = oplan.plan(M, 32, 32, 0.5, 0.5)
         assert st["type"] == po.typ
         assert st["f"] == pytest.approx(po.f, rel=1e-8)
@@ -123,6 +140,7 @@ def test_planner_agrees_with_oracle_gauge(nl):
         prod = (_cm4(P[0]) @ _cc4(P[1]) @ _cm4(P[2]) @ _cc4(P[3]) if st["type"] == 1
                 else _cc4(P[0]) @ _cm4(P[1]) @ _cc4(P[2]) @ _cm4(P[3]))
         assert np.max(np.abs(prod - M)) <= 1e-10 * max(1.0, np.max(np.abs(M)))
+    assert nsym >= 1  # the Fourier matrix
 
 
 def test_planner_type_override_and_pairing(nl):
@@ -217,7 +235,10 @@ def test_reduced_types_match_oracle_stages(nl):
             try:
                 ref = fast.lc_plan(M, 32, 32, 0.5, 0.5, axis=axis)
             except fast.NotApplicable:
-                assert _cplan(nl, M, 32, 32, 0.5, 0.5, opts=_opts(nl, override)) == -3
+                if override == 6:  # falls back to the HA-NsDLCT (Sec. 4.2.2)
+                    assert nl.Plan(M, 32, 32, 0.5, 0.5, type_override=6).stages()["type"] in (1, 2)
+                else:
+                    assert _cplan(nl, M, 32, 32, 0.5, 0.5, opts=_opts(nl, override)) == -3
                 continue
             p = nl.Plan(M, 32, 32, 0.5, 0.5, type_override=override)
             st = p.stages()
@@ -225,12 +246,18 @@ def test_reduced_types_match_oracle_stages(nl):
             for a, b in zip(st["mats"], ref.mats):
                 assert np.max(np.abs(a - b)) <= 1e-10 * max(1.0, np.max(np.abs(b)))
             assert st["f"] == pytest.approx(ref.f, rel=1e-12)
-    # Not applicable: CM-CC-CM with a non-symmetric B, LC for the FT (A = 0).
+    # Not applicable: CM-CC-CM with a non-symmetric B, LC for the FT (A = 0):
+    # an explicit orientation fails, option 6 falls back to the HA-NsDLCT
+    # with the trace-rule type (Sec. 4.2.2; tr B = 2 > 0: type 1).
     assert _cplan(nl, next(synth.symplectic_candidates(7)), opts=_opts(nl, 3)) == -3
     FT = np.block([[np.zeros((2, 2)), np.eye(2)], [-np.eye(2), np.zeros((2, 2))]])
-    assert _cplan(nl, FT, opts=_opts(nl, 6)) == -3
+    assert _cplan(nl, FT, opts=_opts(nl, 4)) == -3
+    assert _cplan(nl, FT, opts=_opts(nl, 5)) == -3
+    pf = nl.Plan(FT, 16, 16, type_override=6)
+    assert pf.stages()["type"] == 1 and pf.passes() == 5
     # The five-pass paths report five passes; reduced stages round-trip.
-    assert nl.Plan(FT, 16, 16).passes() == 5
+    assert nl.Plan(FT, 16, 16, type_override=1).passes() == 5
+    assert nl.Plan(FT, 16, 16).passes() == 3  # symmetric B: CM-CC-CM by default
     st = nl.Plan(FT, 16, 16, type_override=3).stages()
     q = nl.Plan.from_stages(3, st["mats"], 16, 16, 1.0, 1.0)
     assert q.passes() == 3 and q.stages()["type"] == 3
@@ -243,3 +270,35 @@ def _opts(nl, override):
     o = nl.lib.opts()
     o.type_override = override
     return o
+
+
+def test_lie_plans_and_theta_gradient_errors(nl):
+    """nslct_plan_lie plans M0 expm(J S(theta)) (the same stages as planning
+    that matrix directly, under the trace rule even for a symmetric B); a
+    plan made from stages has no theta, so nslct_backward_theta refuses a
+    theta-gradient before any device work, as it refuses the Jacobian of a
+    CM-CC-CM plan chosen for a symmetric B."""
+    from paper_1707_03688_amd import autograd as ag
+    M0 = next(synth.symplectic_candidates(3))
+    th = np.linspace(-0.05, 0.04, 10)
+    a = nl.Plan.lie(M0, th, 32, 24, 0.5, 0.6, symplectic_tol=1e-8).stages()
+    b = nl.Plan(ag.lie_point(M0, th), 32, 24, 0.5, 0.6, symplectic_tol=1e-8).stages()
+    assert a["type"] == b["type"]
+    for x, y in zip(a["mats"], b["mats"]):
+        assert np.array_equal(x, y)
+    FT = np.block([[np.zeros((2, 2)), np.eye(2)], [-np.eye(2), np.zeros((2, 2))]])
+    assert nl.Plan.lie(FT, np.zeros(10), 16, 16).stages()["type"] == 1
+    pf = nl.Plan(FT, 16, 16)
+    assert pf.stages()["type"] == 3
+    with pytest.raises(nl.NslctError) as e:
+        pf.theta_jacobian()
+    assert e.value.code == -6
+    st = b
+    ps = nl.Plan.from_stages(st["type"], st["mats"], 32, 48, 0.5, 0.6)
+    fake = ctypes.c_void_p(1 << 20)
+    gt = (ctypes.c_double * 10)()
+    assert nl.lib.nslct_backward_theta(ps._h, 1, fake, fake, ctypes.c_void_p(2 << 20), gt, None) == -6
+    assert nl.lib.nslct_backward_theta(ps._h, 1, fake, fake, fake, gt, None) == -1  # grad_x == G
+    o = nl.lib.opts()
+    o.det_min = 0.0
+    assert _cplan(nl, M0, opts=o) == -1
