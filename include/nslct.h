@@ -251,6 +251,21 @@ int nslct_backward(nslct_plan_t plan, int count, const void* G, const void* grad
 int nslct_backward_theta(nslct_plan_t plan, int count, const void* G, const void* grad_out, void* grad_x,
                          double grad_theta[10], void* stream);
 
+/* nslct_backward_theta for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same results without any allocation.  The work image and
+ * the 15 sums live in a static device array of the library, 16 MiB + 256
+ * bytes per device (held from the library's first use of that device until
+ * the process ends); images are swept in chunks of up to 16 MiB, so any
+ * count is accepted, and a single image above 16 MiB is NSLCT_E_SIZE
+ * (unreachable with the backward sizes, whose largest image is 1024 x 1024
+ * complex128 = 16 MiB).  The sums are cleared by a kernel at the start of
+ * every call.  Every call on one device shares that device's array: calls
+ * that overlap in time on one device (several host threads, or streams
+ * that run concurrently) race and give wrong results. */
+int nslct_backward_theta_noalloc(nslct_plan_t plan, int count, const void* G, const void* grad_out,
+                                 void* grad_x, double grad_theta[10], void* stream);
+
 /* Host: d(stage entries)/d(theta) of the plan at its own (M0, theta),
  * jac[12][10] row-major (entries in the order of nslct_stages.mats), the
  * planner differentiated as nslct_plan_jacobian does with its step chosen by

@@ -77,6 +77,7 @@ SIGNATURES = {
     "nslct_batch_destroy": (None, [P]),
     "nslct_backward": (I, [P, I, P, P, P, P, P, P]),
     "nslct_backward_theta": (I, [P, I, P, P, P, ctypes.POINTER(D), P]),
+    "nslct_backward_theta_noalloc": (I, [P, I, P, P, P, ctypes.POINTER(D), P]),
     "nslct_plan_theta_jacobian": (I, [P, ctypes.POINTER(D)]),
     "nslct_plan_stage_gradient": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
     "nslct_lie_point": (I, [ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),

@@ -129,10 +129,35 @@ void finish_theta(const PlanData& d, const double* jac, const double sums[15], d
     theta_gradient(jac, gst, grad_theta);
 }
 
+constexpr size_t kNoallocWorkBytes = (size_t)16 << 20;
+constexpr size_t kNoallocSumsBytes = 256;
+
+void* g_scratch[64] = {};  // device address of `scratch`, written once per device under the set-up lock
+
 }  // namespace
 
+// Scratch of the allocation-free backward entry point: the 15 gradient sums
+// (first 256 bytes) and a work region of kNoallocWorkBytes for the inverse
+// chain of G.  Each device holds its own copy of the array.  Host code never
+// passes `scratch` itself to a kernel or a copy (on the host the name is a
+// stand-in, not a device address): it uses g_scratch[device], obtained with
+// hipGetSymbolAddress at the device's set-up.
+static __device__ __align__(256) unsigned char scratch[kNoallocSumsBytes + kNoallocWorkBytes];
+
 namespace nslct {
-hipError_t init_tables_backward() { return init_twiddles_here(); }
+hipError_t init_tables_backward() {
+    hipError_t e = init_twiddles_here();
+    if (e != hipSuccess) return e;
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = ptr;
+    return hipSuccess;
+}
 }  // namespace nslct
 
 extern "C" {
@@ -185,6 +210,38 @@ int nslct_backward_theta(nslct_plan_t plan, int count, const void* G, const void
     if (e == hipSuccess && grad_theta) e = hipMemcpyAsync(host, sums, sizeof host, hipMemcpyDeviceToHost, s);
     const hipError_t ef = hipFreeAsync(buf, s);
     if (e == hipSuccess) e = ef;
+    if (e == hipSuccess && grad_theta) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("backward: ") + hipGetErrorString(e));
+    if (grad_theta) finish_theta(d, jac, host, grad_theta);
+    return NSLCT_OK;
+}
+
+int nslct_backward_theta_noalloc(nslct_plan_t plan, int count, const void* G, const void* grad_out,
+                                 void* grad_x, double grad_theta[10], void* stream) {
+    int rc = check_backward(plan, count, G, grad_out, grad_x);
+    if (rc) return rc;
+    const PlanData& d = plan->d;
+    const size_t es = d.precision == NSLCT_C128 ? 16 : 8;
+    const size_t img = (size_t)d.Nx * d.Ny * es;
+    if (img > kNoallocWorkBytes)
+        return fail(NSLCT_E_SIZE, "an image is larger than the 16 MiB scratch work region");
+    const double* jac = nullptr;
+    if (grad_theta) {
+        rc = plan_jac(plan, &jac);
+        if (rc) return rc;
+    }
+    rc = ensure_device_ready();
+    if (rc) return rc;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    unsigned char* base = (unsigned char*)g_scratch[dev];
+    if (!base) return fail(NSLCT_E_HIP, "scratch address of this device is unknown");
+    hipStream_t s = (hipStream_t)stream;
+    const int chunk = (int)std::min<size_t>((size_t)count, kNoallocWorkBytes / img);
+    double host[15] = {};
+    e = sweep_chunks(d, count, chunk, G, grad_out, base + kNoallocSumsBytes, grad_x, (double*)base, s);
+    if (e == hipSuccess && grad_theta) e = hipMemcpyAsync(host, base, sizeof host, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && grad_theta) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("backward: ") + hipGetErrorString(e));
     if (grad_theta) finish_theta(d, jac, host, grad_theta);
