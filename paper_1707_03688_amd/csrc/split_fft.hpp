@@ -9,6 +9,15 @@
 // and the product is accumulated in FP32 as W_hi X_hi + W_hi X_lo + W_lo X_hi
 // (the lo * lo term is below the half-precision rounding of the others).
 //
+// FP16 has a narrow exponent range (largest finite 65504): an unnormalised
+// line DFT grows its values by up to 16 per radix-16 stage, and a 4096-long
+// column pass starts from row DFT outputs that are up to 4096 times the
+// image's mean.  Each butterfly's inputs are therefore scaled by a power of
+// two 2^k (exact) so that their largest magnitude lies in [2^13, 2^14) before
+// the split, and the FP32 products are scaled back by 2^-k.  The four lanes
+// that supply one butterfly (one column of the B operand) share k.  BF16
+// parts keep the FP32 exponent range and are not scaled.
+//
 // Operand layout of the 16x16x32 instruction (checked on the device): lane l
 // holds A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16], e = 0..7, and
 // receives D[4 (l / 16) + e][l % 16], e = 0..3.  The K index is ordered
@@ -108,6 +117,7 @@ __device__ __forceinline__ void split_stage(cplx<float>* lds, int Ns, const Spli
         line_of[b] = line;
         base_of[b] = (j / Ns) * Ns * 16 + k;
         typename K::V bh, bl;
+        cplx<float> xs[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int q = 4 * g + e;
@@ -118,11 +128,28 @@ __device__ __forceinline__ void split_stage(cplx<float>* lds, int Ns, const Spli
                 if (S > 0) w.im = -w.im;
                 x = cmul(x, w);
             }
-            const Ek hr = (Ek)x.re, hi_ = (Ek)x.im;
+            xs[e] = x;
+        }
+        int kexp = 0;
+        if constexpr (KIND == 0) {
+            float m = 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) m = fmaxf(m, fmaxf(fabsf(xs[e].re), fabsf(xs[e].im)));
+            m = fmaxf(m, __shfl_xor(m, 16));
+            m = fmaxf(m, __shfl_xor(m, 32));
+            int ex;
+            (void)frexpf(m, &ex);  // m in [2^(ex-1), 2^ex); ex = 0 for m = 0
+            kexp = 14 - ex;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xs[e] = {ldexpf(xs[e].re, kexp), ldexpf(xs[e].im, kexp)};
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const Ek hr = (Ek)xs[e].re, hi_ = (Ek)xs[e].im;
             bh[2 * e] = hr;
             bh[2 * e + 1] = hi_;
-            bl[2 * e] = (Ek)(x.re - (float)hr);
-            bl[2 * e + 1] = (Ek)(x.im - (float)hi_);
+            bl[2 * e] = (Ek)(xs[e].re - (float)hr);
+            bl[2 * e + 1] = (Ek)(xs[e].im - (float)hi_);
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -130,6 +157,10 @@ __device__ __forceinline__ void split_stage(cplx<float>* lds, int Ns, const Spli
             d = K::mma(W.hi[si][h], bh, d);
             d = K::mma(W.hi[si][h], bl, d);
             d = K::mma(W.lo[si][h], bh, d);
+            if constexpr (KIND == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) d[c] = ldexpf(d[c], -kexp);
+            }
             y[b][2 * h] = {d[0], d[1]};      // y_{8h+2g}
             y[b][2 * h + 1] = {d[2], d[3]};  // y_{8h+2g+1}
         }
