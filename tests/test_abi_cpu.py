@@ -302,3 +302,26 @@ def test_lie_plans_and_theta_gradient_errors(nl):
     o = nl.lib.opts()
     o.det_min = 0.0
     assert _cplan(nl, M0, opts=o) == -1
+
+
+def test_box_check_agrees_with_oracle_predicate(nl):
+    """nslct_plan_box_check(0.5) equals the oracle's phase-space predicate
+    (sampling.well_sampled, itself pinned corner by corner) on plans of both
+    types with stage matrices from tiny to large, so both outcomes occur."""
+    from oracle import sampling
+    rng = np.random.default_rng(17)
+    seen = set()
+    for k in range(60):
+        typ = 1 + k % 2
+        scale = (0.02, 0.1, 0.4, 1.5)[k % 4]
+        mats = []
+        for _ in range(4):
+            X = rng.normal(size=(2, 2)) * scale
+            mats.append(0.5 * (X + X.T))
+        Nx, Ny, dx, dy = 32, 48, 0.6, 0.45
+        po = oplan.plan_from_stages(typ, mats, Nx, Ny, dx, dy)
+        pg = nl.Plan.from_stages(typ, mats, Nx, Ny, dx, dy)
+        ok = sampling.well_sampled(po)
+        assert pg.box_check(0.5) == ok
+        seen.add(ok)
+    assert seen == {True, False}

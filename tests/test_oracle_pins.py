@@ -10,7 +10,6 @@ off-by-one centring, swapped stages) make at least one pin fail.
 from __future__ import annotations
 
 import math
-import os
 
 import numpy as np
 import pytest
@@ -166,9 +165,9 @@ def test_printed_additivity_g1():
 
 
 @pytest.mark.slow
-@pytest.mark.skipif(not os.environ.get("NSLCT_SLOW"), reason="about 2 minutes; set NSLCT_SLOW=1")
 def test_printed_accuracy_g2_m2():
-    """NMSE_acc for g2 / M2 (Sec. 5.1): paper prints 1.1e-3 (about 2 minutes)."""
+    """NMSE_acc for g2 / M2 (Sec. 5.1): paper prints 1.1e-3 (about 2 minutes:
+    the direct sum from the 269^2-point truth grid onto 165^2 points)."""
     pv = printed_values()
     M = symplectic.project(paper_matrices()["M2"])
     N, d = 165, 0.2
@@ -408,14 +407,69 @@ def test_hermite_gaussians_orthonormal():
             assert ip == pytest.approx(1.0 if k == l else 0.0, abs=1e-10)
 
 
+def _cm4(P):
+    return np.block([[np.eye(2), np.zeros((2, 2))], [np.asarray(P), np.eye(2)]])
+
+
+def _cc4(B):
+    return np.block([[np.eye(2), np.asarray(B)], [np.zeros((2, 2)), np.eye(2)]])
+
+
+def _corner_boxes(stage_list, box0):
+    """Half-widths of the phase-space box after each stage: the box's 16
+    corners (x, y, wx, wy) pushed through the stage's 4x4 matrix, the largest
+    |component| taken over the corners (a linear map of a box centred at the
+    origin reaches its extent at a corner)."""
+    signs = np.array([[sx, sy, su, sv] for sx in (-1, 1) for sy in (-1, 1) for su in (-1, 1) for sv in (-1, 1)])
+    out, box = [], np.asarray(box0, dtype=float)
+    for S in stage_list:
+        corners = signs * box
+        box = np.max(np.abs(corners @ S.T), axis=0)
+        out.append(tuple(box))
+    return out
+
+
 def test_sampling_box_diagnostic():
-    """The phase-space box stays put through identity-like stages and grows
-    by the gamma row sums otherwise (eqs. HA12, HA20)."""
+    """The support-box predicate of the phase-space reading (Sec. 4.2.1: a CM
+    adds C z to the frequencies, eq. HA12; a CC adds B w to the positions,
+    eq. HA20), pinned to an independent computation: the stages as 4x4
+    matrices in application order (checked by multiplying back to M, right
+    factor first), the box of the reading (|x| <= N dx / 4, |w| <= pi / (2 dx))
+    pushed through them corner by corner.  Plans with four nonzero,
+    unequal stages of both types, and the pure CM."""
+    draws = _draws(5, 8)
+    checked = 0
+    for M in draws:
+        for typ in (1, 2):
+            p = oplan.plan(M, 24, 40, 0.35, 0.5, typ=typ)
+            P = p.mats
+            if typ == 1:  # G = CM(P1) CC(B') CM(P3) CC(H) g: CC(H) acts first
+                seq = [_cc4(P[3]), _cm4(P[2]), _cc4(P[1]), _cm4(P[0])]
+            else:         # G = CC(H1) CM(Q1) CC(B1') CM(Q3) g
+                seq = [_cm4(P[3]), _cc4(P[2]), _cm4(P[1]), _cc4(P[0])]
+            prod = seq[3] @ seq[2] @ seq[1] @ seq[0]
+            assert np.max(np.abs(prod - M)) <= 1e-9 * max(1.0, np.max(np.abs(M)))
+            if min(np.max(np.abs(X)) for X in P) < 1e-3:
+                continue  # a (near) zero stage would not tell the order apart
+            box0 = (24 * 0.35 / 4, 40 * 0.5 / 4, math.pi / (2 * 0.35), math.pi / (2 * 0.5))
+            ref = _corner_boxes(seq, box0)
+            got = sampling.stage_boxes(p)
+            assert len(got) == 4
+            for a, b in zip(got, ref):
+                assert np.allclose(a, b, rtol=1e-13, atol=0)
+            lim = (24 * 0.35 / 2, 40 * 0.5 / 2, math.pi / 0.35, math.pi / 0.5)
+            assert sampling.well_sampled(p) == all(all(b <= l * (1 + 1e-12) for b, l in zip(bx, lim))
+                                                  for bx in ref)
+            checked += 1
+    assert checked >= 8
+    C = np.array([[0.3, -0.7], [-0.7, 0.2]])
+    pc = oplan.plan_from_stages(0, (C,), 16, 16, 0.5, 0.5)
+    box0 = (16 * 0.5 / 4, 16 * 0.5 / 4, math.pi, math.pi)
+    assert np.allclose(sampling.stage_boxes(pc)[0], _corner_boxes([_cm4(C)], box0)[0], rtol=1e-13)
+    # Both outcomes occur: identity-like stages stay inside, a large CC not.
     Z = np.zeros((2, 2))
-    p = oplan.plan_from_stages(1, (Z, Z, Z, Z), 16, 16, 0.5, 0.5)
-    assert sampling.well_sampled(p)
-    p = oplan.plan_from_stages(1, (Z, np.eye(2) * 40, Z, Z), 16, 16, 0.5, 0.5)
-    assert not sampling.well_sampled(p)
+    assert sampling.well_sampled(oplan.plan_from_stages(1, (Z, Z, Z, Z), 16, 16, 0.5, 0.5))
+    assert not sampling.well_sampled(oplan.plan_from_stages(1, (Z, np.eye(2) * 40, Z, Z), 16, 16, 0.5, 0.5))
 
 
 # --------------------------------------------------------------------------
