@@ -28,10 +28,38 @@ if ROOT not in sys.path:
 
 METRIC = "NsLCT/s @1024² c64 + %HBM peak; split-prec vs FP32 plain at relL2≤1e-4"
 HBM_PEAK_GBPS = 8000.0
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by the
-# copy-kernel calibration (profiles/nslct_pass_1024_c64_forward.md).  Set to
-# None whenever the kernels change until the counters are taken again.
-TRAFFIC_BYTES = {"rows": 16893 * 1024, "cols": 16925 * 1024}
+# HBM bytes per launch of the two 1024-long pass kernels: rocprofv3
+# FETCH_SIZE / WRITE_SIZE scaled by the copy-kernel calibration, read from the
+# kept profile, which records a hash of the kernel sources it was taken with;
+# when the sources have changed since, the traffic is unknown (None).
+PROFILE = os.path.join(ROOT, "profiles", "nslct_pass_1024_c64_forward.md")
+KERNEL_SOURCES = ("fft_engine.hpp", "pass_kernels.hpp", "nslct.hip")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1707_03688_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile() -> dict:
+    """{"rows": bytes, "cols": bytes} from the profile's traffic line, or
+    {} when the profile is missing or was taken with other kernel sources."""
+    import re
+    try:
+        with open(PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return {}
+    m = re.search(r"traffic-per-launch: rows=(\d+) cols=(\d+) sources=([0-9a-f]+)", text)
+    if not m or m.group(3) != kernel_source_hash():
+        return {}
+    return {"rows": int(m.group(1)), "cols": int(m.group(2))}
+
+
 KERNEL_NAMES = {"rows": "nslct_pass<float, 1024, false, 4> (passes 0, 2, 4: row lines)",
                 "cols": "nslct_pass<float, 1024, true, 4> (passes 1, 3: column lines)"}
 
@@ -49,24 +77,56 @@ def draw_matrix(seed: int, N: int, d: float, nl):
     raise RuntimeError("no acceptable draw")
 
 
-def cpu_baseline(M_plan_stages, g, budget_s: float = 20.0):
-    """The FP64 oracle (dense-DFT chain) on the host, same image and stages."""
-    import numpy as np
+def host_info() -> dict:
+    """CPU model, logical CPU count and the affinity set of this process."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    try:
+        aff = sorted(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        aff = list(range(os.cpu_count() or 1))
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "affinity": len(aff),
+            "affinity_set": _ranges(aff)}
+
+
+def _ranges(xs) -> str:
+    out, start, prev = [], None, None
+    for x in xs:
+        if start is None:
+            start = prev = x
+        elif x == prev + 1:
+            prev = x
+        else:
+            out.append(f"{start}-{prev}" if prev > start else f"{start}")
+            start = prev = x
+    if start is not None:
+        out.append(f"{start}-{prev}" if prev > start else f"{start}")
+    return ",".join(out)
+
+
+def cpu_baseline(M_plan_stages, g, budget_s: float = 20.0, threads=None):
+    """The FP64 oracle (dense-DFT chain) on the host, same image and stages,
+    with the BLAS pool limited to `threads` (None: as configured)."""
     from oracle import chain, plan as oplan
     typ, mats, N, d = M_plan_stages
     po = oplan.plan_from_stages(typ, mats, N, N, d, d)
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count()
-    runs, t_total, out = 0, 0.0, None
-    while runs < 1 or (t_total < budget_s and runs < 5):
-        t0 = time.perf_counter()
-        out = chain.forward(po, g)
-        t_total += time.perf_counter() - t0
-        runs += 1
-    return runs / t_total, threads, runs, out
+    from threadpoolctl import threadpool_info, threadpool_limits
+    with threadpool_limits(limits=threads):
+        used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        runs, t_total, out = 0, 0.0, None
+        while runs < 1 or (t_total < budget_s and runs < 5):
+            t0 = time.perf_counter()
+            out = chain.forward(po, g)
+            t_total += time.perf_counter() - t0
+            runs += 1
+    return runs / t_total, used, runs, out
 
 
 def cpu_fft_chain(st, g, N, d, budget_s: float = 10.0):
@@ -460,7 +520,7 @@ def main():
                    "Nx": N, "Ny": N, "precision": "c64", "type": st["type"], "draw": draw,
                    "ring_pairs": R, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": TRAFFIC_BYTES[dom],
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile().get(dom),
                      "kernel": KERNEL_NAMES[dom], "avg_launch_us": kern_ms[dom] * 1e3,
                      "launches_per_transform": len(kernels[dom])},
         "pass_us": [round(v * 1e3, 3) for v in pass_ms],
@@ -489,10 +549,12 @@ def main():
         result["fwd_bwd_512"] = bwd
     if not args.no_cpu:
         rate, threads, runs, ref = cpu_baseline((st["type"], st["mats"], N, d), g)
+        rate1, _, runs1, _ = cpu_baseline((st["type"], st["mats"], N, d), g, budget_s=5.0, threads=1)
         from oracle import chain
         result["cpu_baseline"] = {"value": rate, "unit": "NsLCT/s", "cores": threads, "kind": "oracle",
                                   "sample": f"{runs} forward transform(s) of the same 1024x1024 image "
-                                            "by the FP64 dense-DFT oracle chain"}
+                                            "by the FP64 dense-DFT oracle chain",
+                                  "one_core": {"value": rate1, "runs": runs1}, **host_info()}
         result["rel_l2_vs_fp64_oracle"] = chain.rel_l2(G, ref)
         frate, fruns, fout = cpu_fft_chain(st, g, N, d)
         result["cpu_fft_chain"] = {"value": frate, "unit": "NsLCT/s", "threads": os.cpu_count(),

@@ -35,3 +35,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_host_info_and_ranges():
+    info = bench.host_info()
+    assert info["os_cpu_count"] >= 1 and info["affinity"] >= 1
+    assert bench._ranges([0, 1, 2, 5, 7, 8]) == "0-2,5,7-8"
+
+
+def test_traffic_is_read_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    prof = tmp_path / "p.md"
+    h = bench.kernel_source_hash()
+    prof.write_text(f"x\\ntraffic-per-launch: rows=17 cols=19 sources={h}\\n")
+    monkeypatch.setattr(bench, "PROFILE", str(prof))
+    assert bench.traffic_from_profile() == {"rows": 17, "cols": 19}
+    prof.write_text("traffic-per-launch: rows=17 cols=19 sources=0123456789abcdef\\n")
+    assert bench.traffic_from_profile() == {}

@@ -42,7 +42,7 @@ def _batch(nl, sizes, seed, precision="c64", rect=False):
 
 @pytest.mark.parametrize("rect", [False, True])
 def test_batched_matches_loop_bitwise_and_oracle(torch, nl, rect):
-    sizes = [64, 384, 128, 768, 256, 192, 512, 64, 128, 384]
+    sizes = [64, 384, 128, 768, 256, 192, 512, 64, 128, 384, 1024]
     b, oplans = _batch(nl, sizes, seed=31, rect=rect)
     g = synth.complex_normal((b.total,), seed=2)
     x = torch.from_numpy(g).to(torch.complex64).cuda()
@@ -53,11 +53,10 @@ def test_batched_matches_loop_bitwise_and_oracle(torch, nl, rect):
     assert torch.equal(out_graph, out_loop)
     assert torch.equal(out_plain, out_loop)
     got = out_graph.cpu().numpy()
-    for o, p, po in zip(b.offsets, b.plans, oplans):
+    for o, p, po in zip(b.offsets, b.plans, oplans):  # every image, 64^2 to 1024^2
         gi = g[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny)
-        if p.Nx * p.Ny <= 384 * 384:
-            ref = chain.forward(po, gi)
-            assert chain.rel_l2(got[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny), ref) <= 1e-5
+        ref = chain.forward(po, gi)
+        assert chain.rel_l2(got[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny), ref) <= 1e-5
     back = b.inverse(out_graph).cpu().numpy()
     assert chain.rel_l2(back, g) <= 1e-5
 

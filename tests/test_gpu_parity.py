@@ -228,3 +228,43 @@ def test_unitarity_and_adjoint_at_4096(torch, nl):
     back = pg.inverse(Lx)
     err = (torch.linalg.vector_norm(back - x) / torch.linalg.vector_norm(x)).item()
     assert err <= 1e-5
+
+
+def _special_matrices():
+    """Matrices outside the configs' generator (whose B always has det B < 0
+    and a nonzero trace): M_self of Sec. 6.2 (eq. self04, projected; det B > 0,
+    tr B < 0), the identity (B = 0, A = D = I: the pure-CM case with C = 0),
+    and a matrix with tr B = 0 exactly and a non-symmetric B,
+    (0, B; -B^-T, 0)(I, 0; P, I) = (B P, B; -B^-T, 0), which is symplectic for
+    any invertible B and symmetric P."""
+    Mself = symplectic.project(paper_matrices()["Mself"])
+    B = np.array([[1.0, 0.9], [-0.3, -1.0]])
+    P = np.array([[0.5, 0.2], [0.2, -0.3]])
+    Mtr0 = np.block([[B @ P, B], [-np.linalg.inv(B).T, np.zeros((2, 2))]])
+    return {"self": Mself, "identity": np.eye(4), "trace0": Mtr0}
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+@pytest.mark.parametrize("name", ["self", "identity", "trace0"])
+def test_special_matrices_match_oracle(torch, nl, name, precision):
+    """Planned by the library (nslct_plan), compared at the planner's stages
+    with the oracle, forward and inverse: M_self plans CC-CM-CC-CM (tr B < 0),
+    the identity plans the pure CM and returns its input, tr B = 0 plans
+    CM-CC-CM-CC (reading: type 1)."""
+    M = _special_matrices()[name]
+    assert symplectic.residual(M) <= 1e-12
+    Nx, Ny, dx, dy = 96, 64, 0.3, 0.35
+    pg = nl.Plan(M, Nx, Ny, dx, dy, precision=precision)
+    st = pg.stages()
+    assert st["type"] == {"self": 2, "identity": 0, "trace0": 1}[name]
+    if name == "trace0":
+        assert np.trace(M[:2, 2:]) == 0.0
+    nm = 1 if st["type"] == 0 else 4
+    po = oplan.plan_from_stages(st["type"], st["mats"][:nm], Nx, Ny, dx, dy)
+    g = synth.complex_normal((Nx, Ny), seed=61)
+    G = pg.forward(_to_gpu(torch, g, precision)).cpu().numpy()
+    assert chain.rel_l2(G, chain.forward(po, g)) <= TOL[precision]
+    Gi = pg.inverse(_to_gpu(torch, g, precision)).cpu().numpy()
+    assert chain.rel_l2(Gi, chain.inverse(po, g)) <= TOL[precision]
+    if name == "identity":
+        assert chain.rel_l2(G, g) <= TOL[precision]
