@@ -39,6 +39,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <thread>
 #include <vector>
 
 namespace nslct {
@@ -110,7 +111,8 @@ struct Gauge {
             const M2 Dp = sub(b.D, mul(b.C, H));
             *dt = det(Bp);
             if (!(std::fabs(*dt) >= dmin)) return false;
-            const M2 Bi{Bp.a22 / *dt, -Bp.a12 / *dt, -Bp.a21 / *dt, Bp.a11 / *dt};
+            const double r = 1.0 / *dt;
+            const M2 Bi{Bp.a22 * r, -Bp.a12 * r, -Bp.a21 * r, Bp.a11 * r};
             X1 = mul(minus_eye(Dp), Bi);   // P1 = (D' - I) B'^-1
             X3 = mul(Bi, minus_eye(b.A));  // P3 = B'^-1 (A - I)
             sym3(X1, out[0]);
@@ -122,7 +124,8 @@ struct Gauge {
             const M2 Ap = sub(b.A, mul(H, b.C));
             *dt = det(Bp);
             if (!(std::fabs(*dt) >= dmin)) return false;
-            const M2 Bi{Bp.a22 / *dt, -Bp.a12 / *dt, -Bp.a21 / *dt, Bp.a11 / *dt};
+            const double r = 1.0 / *dt;
+            const M2 Bi{Bp.a22 * r, -Bp.a12 * r, -Bp.a21 * r, Bp.a11 * r};
             X1 = mul(minus_eye(b.D), Bi);  // Q1 = (D - I) B1'^-1
             X3 = mul(Bi, minus_eye(Ap));   // Q3 = B1'^-1 (A1' - I)
             sym3(H, out[0]);
@@ -315,32 +318,68 @@ GaugeOut solve(const Gauge& g, double mmax, const double* start = nullptr) {
     std::vector<std::pair<double, std::array<int, 3>>> cells;
     if (!start) cells.reserve(dim == 2 ? G * G : G * G * G);
     if (!start) {
-        double s[3] = {0, 0, 0};
+        // The grid's rows are evaluated by up to 16 host threads; the cells
+        // are gathered in row order (the same list as a serial sweep).
         const int G3 = dim == 3 ? G : 1;
-        for (int i = 0; i < G; ++i)
-            for (int j = 0; j < G; ++j)
-                for (int k = 0; k < G3; ++k) {
-                    s[0] = -R + step * i;
-                    s[1] = -R + step * j;
-                    s[2] = -R + step * k;
-                    const double f = fs(s);
-                    if (std::isfinite(f)) cells.push_back({f, {i, j, k}});
-                }
+        const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::vector<std::pair<double, std::array<int, 3>>>> part(nth);
+        for (auto& pv : part) pv.reserve((size_t)(G / nth + 1) * G * G3);
+        auto rows = [&](int t) {
+            double s[3] = {0, 0, 0};
+            for (int i = t; i < G; i += nth)
+                for (int j = 0; j < G; ++j)
+                    for (int k = 0; k < G3; ++k) {
+                        s[0] = -R + step * i;
+                        s[1] = -R + step * j;
+                        s[2] = -R + step * k;
+                        const double f = fs(s);
+                        if (std::isfinite(f)) part[t].push_back({f, {i, j, k}});
+                    }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nth; ++t) pool.emplace_back(rows, t);
+        rows(0);
+        for (auto& th : pool) th.join();
+        std::vector<size_t> at(nth, 0);
+        for (int i = 0; i < G; ++i) {  // row i was swept by thread i mod nth
+            auto& pv = part[i % nth];
+            size_t& a = at[i % nth];
+            while (a < pv.size() && pv[a].second[0] == i) cells.push_back(pv[a++]);
+        }
     }
     if (!start) {
         if (cells.empty()) return out;
-        std::sort(cells.begin(), cells.end(),
-                  [](const auto& x, const auto& y) { return x.first < y.first; });
-        std::vector<std::array<int, 3>> seeds;
-        for (const auto& cell : cells) {
-            bool far = true;
-            for (const auto& sd : seeds) {
-                int dmax = 0;
-                for (int k = 0; k < dim; ++k) dmax = std::max(dmax, std::abs(cell.second[k] - sd[k]));
-                if (dmax <= 3) far = false;
+        // Seeds: the best cells in increasing objective, each more than three
+        // cells away from the seeds already taken, at most 16.  Only the head
+        // of the order is needed: the best `head` cells are selected and
+        // sorted, and the full order is taken only if they hold fewer than 16
+        // seeds (same seeds either way; ties ordered by cell index).
+        auto less = [](const std::pair<double, std::array<int, 3>>& x,
+                       const std::pair<double, std::array<int, 3>>& y) {
+            return x.first < y.first || (x.first == y.first && x.second < y.second);
+        };
+        auto pick = [&](size_t n, std::vector<std::array<int, 3>>& seeds) {
+            seeds.clear();
+            for (size_t c = 0; c < n; ++c) {
+                const auto& cell = cells[c];
+                bool far = true;
+                for (const auto& sd : seeds) {
+                    int dmax = 0;
+                    for (int k = 0; k < dim; ++k) dmax = std::max(dmax, std::abs(cell.second[k] - sd[k]));
+                    if (dmax <= 3) far = false;
+                }
+                if (far) seeds.push_back(cell.second);
+                if (seeds.size() >= 16) return true;
             }
-            if (far) seeds.push_back(cell.second);
-            if (seeds.size() >= 16) break;
+            return false;
+        };
+        std::vector<std::array<int, 3>> seeds;
+        const size_t head = std::min<size_t>(cells.size(), 4096);
+        std::nth_element(cells.begin(), cells.begin() + (head - 1), cells.end(), less);
+        std::sort(cells.begin(), cells.begin() + head, less);
+        if (!pick(head, seeds) && head < cells.size()) {
+            std::sort(cells.begin(), cells.end(), less);
+            pick(cells.size(), seeds);
         }
         for (const auto& sd : seeds) starts.push_back({-R + step * sd[0], -R + step * sd[1], -R + step * sd[2]});
     }
@@ -943,6 +982,205 @@ void lie_point(const double abcd[16], const double theta[10], double* M) {
     mat4_mul(abcd, E, M);
 }
 
+namespace {
+
+// Central differences of the planner along theta with the decomposition type
+// held and the gauge followed from `base_h` (the minimiser at theta0).
+int jacobian_followed(const double abcd[16], const double theta0[10], int Nx, int Ny, double dx, double dy,
+                      const nslct_opts& o, int base_type, const double base_h[3], double h,
+                      double jac[12 * 10], std::string* err) {
+    int rc = 0;
+    nslct_opts of = o;
+    of.type_override = base_type;  // stay on one decomposition type
+    for (int i = 0; i < 10; ++i) {
+        double tp[10], tm[10], Mp[16], Mm[16];
+        for (int k = 0; k < 10; ++k) tp[k] = tm[k] = theta0[k];
+        tp[i] += h;
+        tm[i] -= h;
+        lie_point(abcd, tp, Mp);
+        lie_point(abcd, tm, Mm);
+        PlanData pp, pm;
+        rc = build_plan_from(Mp, Nx, Ny, dx, dy, of, &pp, err, base_h, false);
+        if (!rc) rc = build_plan_from(Mm, Nx, Ny, dx, dy, of, &pm, err, base_h, false);
+        if (rc) return rc;
+        if (pp.st.type != pm.st.type) {
+            *err = "decomposition type changes within the difference step";
+            return NSLCT_E_NO_DECOMPOSITION;
+        }
+        for (int m = 0; m < 4; ++m)
+            for (int k = 0; k < 3; ++k) jac[(3 * m + k) * 10 + i] = (pp.st.mats[m][k] - pm.st.mats[m][k]) / (2 * h);
+    }
+    return NSLCT_OK;
+}
+
+// The twelve stage entries (order of nslct_stages.mats) of a type-1/2 gauge
+// h for the matrix M(theta); false where B' is not invertible.
+bool stage_entries(const Gauge& g, const double h[3], double e[12]) {
+    double st[4][3], dt;
+    if (!g.stages(h, st, &dt)) return false;
+    for (int m = 0; m < 4; ++m)
+        for (int k = 0; k < 3; ++k) e[3 * m + k] = st[m][k];
+    return true;
+}
+
+// Solves the 3 x 3 system A x = b (Gaussian elimination, partial pivoting);
+// false when A is singular to working precision.
+bool solve3(double A[3][3], double b[3], double x[3]) {
+    int p[3] = {0, 1, 2};
+    double a[3][4];
+    double amax = 0;
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) {
+            a[r][c] = A[r][c];
+            amax = std::max(amax, std::fabs(A[r][c]));
+        }
+        a[r][3] = b[r];
+    }
+    if (!(amax > 0)) return false;
+    for (int c = 0; c < 3; ++c) {
+        int best = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (std::fabs(a[p[r]][c]) > std::fabs(a[p[best]][c])) best = r;
+        std::swap(p[c], p[best]);
+        const double piv = a[p[c]][c];
+        if (std::fabs(piv) <= 1e-13 * amax) return false;
+        for (int r = c + 1; r < 3; ++r) {
+            const double f = a[p[r]][c] / piv;
+            for (int k = c; k < 4; ++k) a[p[r]][k] -= f * a[p[c]][k];
+        }
+    }
+    for (int c = 2; c >= 0; --c) {
+        double v = a[p[c]][3];
+        for (int k = c + 1; k < 3; ++k) v -= a[p[c]][k] * x[k];
+        x[c] = v / a[p[c]][c];
+    }
+    return true;
+}
+
+// d(stage entries)/d(theta) of a type-1/2 plan by the implicit function
+// theorem.  The eq. HA24 minimiser sits where `need` stage entries vanish
+// (the |.| kinks of the gamma ratios), need = 3 - (number of feasibility
+// equations): with the kink set held, the gauge H(theta) is the solution of
+//   F(H, theta) = [feasibility c(M) . h - rhs(M); e_k(H, M), k in the kink set] = 0,
+// so dH/dtheta = -F_H^-1 F_theta and d(stages)/dtheta = S_theta + S_H dH/dtheta.
+// The partial derivatives of these closed-form functions are central
+// differences with steps of 1e-6 (no gauge search is repeated).  Returns
+// false (the caller falls back to re-solved differences) when fewer than
+// `need` entries vanish or no choice of them gives a regular F_H.
+bool jacobian_implicit(const PlanData& p, double jac[12 * 10]) {
+    const int type = p.st.type;
+    if (type != 1 && type != 2) return false;
+    double M[16];
+    lie_point(p.abcd0, p.theta, M);
+    const Blocks b0 = split(M);
+    double bmax = std::max({std::fabs(b0.B.a11), std::fabs(b0.B.a12), std::fabs(b0.B.a21), std::fabs(b0.B.a22)});
+    const double dmin = p.opts.det_min * std::max(1.0, bmax * bmax);
+    auto gauge_at = [&](const double* theta) {
+        double Mt[16];
+        lie_point(p.abcd0, theta, Mt);
+        return Gauge{split(Mt), type, dmin};
+    };
+    const double* h0 = p.st.h;
+    const Gauge g0 = gauge_at(p.theta);
+    double c[3], rhs;
+    g0.equation(c, &rhs);
+    double mmax = 0;
+    for (double v : M) mmax = std::max(mmax, std::fabs(v));
+    const bool plane = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) > 1e-12 * std::max(1.0, mmax);
+    const int need = plane ? 2 : 3;
+    double e0[12];
+    if (!stage_entries(g0, h0, e0)) return false;
+    double emax = 0;
+    for (double v : e0) emax = std::max(emax, std::fabs(v));
+    std::vector<int> kink;
+    for (int k = 0; k < 12; ++k)
+        if (std::fabs(e0[k]) <= 1e-9 * (1 + emax)) kink.push_back(k);
+    if ((int)kink.size() < need) return false;
+    // F(H, theta) for a chosen kink subset.
+    auto F = [&](const Gauge& g, const double* h, const int* ks, double* out) {
+        double e[12];
+        if (!stage_entries(g, h, e)) return false;
+        int n = 0;
+        if (plane) {
+            double cc[3], rr;
+            g.equation(cc, &rr);
+            out[n++] = cc[0] * h[0] + cc[1] * h[1] + cc[2] * h[2] - rr;
+        }
+        for (int i = 0; i < need; ++i) out[n++] = e[ks[i]];
+        return true;
+    };
+    const double sh = 1e-6 * (1 + std::fabs(h0[0]) + std::fabs(h0[1]) + std::fabs(h0[2]));
+    const double st = 1e-6;
+    // Pick the kink subset with the best-conditioned F_H.
+    double FH[3][3] = {};
+    int best[3] = {0, 0, 0};
+    double best_det = 0;
+    const int nk = (int)kink.size();
+    for (int a = 0; a < nk; ++a)
+        for (int bb = a + 1; bb < nk; ++bb)
+            for (int cc3 = need == 3 ? bb + 1 : nk - 1; cc3 < nk; ++cc3) {
+                int ks[3] = {kink[a], kink[bb], need == 3 ? kink[cc3] : 0};
+                double J[3][3];
+                bool ok = true;
+                for (int j = 0; j < 3 && ok; ++j) {
+                    double hp[3] = {h0[0], h0[1], h0[2]}, hm[3] = {h0[0], h0[1], h0[2]};
+                    hp[j] += sh;
+                    hm[j] -= sh;
+                    double fp[3], fm[3];
+                    ok = F(g0, hp, ks, fp) && F(g0, hm, ks, fm);
+                    for (int r = 0; r < 3 && ok; ++r) J[r][j] = (fp[r] - fm[r]) / (2 * sh);
+                }
+                if (!ok) continue;
+                const double d = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                if (std::fabs(d) > std::fabs(best_det)) {
+                    best_det = d;
+                    std::memcpy(best, ks, sizeof best);
+                    std::memcpy(FH, J, sizeof FH);
+                }
+                if (need == 2) break;  // the inner index is unused
+            }
+    if (!(std::fabs(best_det) > 0)) return false;
+    double dH[3][10];
+    double S_theta[12][10];
+    for (int i = 0; i < 10; ++i) {
+        double tp[10], tm[10];
+        for (int k = 0; k < 10; ++k) tp[k] = tm[k] = p.theta[k];
+        tp[i] += st;
+        tm[i] -= st;
+        const Gauge gp = gauge_at(tp), gm = gauge_at(tm);
+        double fp[3], fm[3], ep[12], em[12];
+        if (!F(gp, h0, best, fp) || !F(gm, h0, best, fm)) return false;
+        if (!stage_entries(gp, h0, ep) || !stage_entries(gm, h0, em)) return false;
+        double Ft[3], x[3];
+        for (int r = 0; r < 3; ++r) Ft[r] = -(fp[r] - fm[r]) / (2 * st);
+        double A[3][3];
+        std::memcpy(A, FH, sizeof A);
+        if (!solve3(A, Ft, x)) return false;
+        for (int r = 0; r < 3; ++r) dH[r][i] = x[r];
+        for (int m = 0; m < 12; ++m) S_theta[m][i] = (ep[m] - em[m]) / (2 * st);
+    }
+    double S_H[12][3];
+    for (int j = 0; j < 3; ++j) {
+        double hp[3] = {h0[0], h0[1], h0[2]}, hm[3] = {h0[0], h0[1], h0[2]};
+        hp[j] += sh;
+        hm[j] -= sh;
+        double ep[12], em[12];
+        if (!stage_entries(g0, hp, ep) || !stage_entries(g0, hm, em)) return false;
+        for (int m = 0; m < 12; ++m) S_H[m][j] = (ep[m] - em[m]) / (2 * sh);
+    }
+    for (int m = 0; m < 12; ++m)
+        for (int i = 0; i < 10; ++i) {
+            double v = S_theta[m][i];
+            for (int j = 0; j < 3; ++j) v += S_H[m][j] * dH[j][i];
+            jac[m * 10 + i] = v;
+        }
+    return true;
+}
+
+}  // namespace
+
 int plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny, double dx, double dy,
                   const nslct_opts& o, double h, double jac[12 * 10], std::string* err) {
     if (!(h > 0) || h > 1e-2) {
@@ -954,27 +1192,8 @@ int plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny
     PlanData base;
     int rc = build_plan_from(M0, Nx, Ny, dx, dy, o, &base, err, nullptr, false);
     if (rc) return rc;
-    nslct_opts of = o;
-    of.type_override = base.st.type == 0 ? 0 : base.st.type;  // stay on one decomposition type
-    for (int i = 0; i < 10; ++i) {
-        double tp[10], tm[10], Mp[16], Mm[16];
-        for (int k = 0; k < 10; ++k) tp[k] = tm[k] = theta0[k];
-        tp[i] += h;
-        tm[i] -= h;
-        lie_point(abcd, tp, Mp);
-        lie_point(abcd, tm, Mm);
-        PlanData pp, pm;
-        rc = build_plan_from(Mp, Nx, Ny, dx, dy, of, &pp, err, base.st.h, false);
-        if (!rc) rc = build_plan_from(Mm, Nx, Ny, dx, dy, of, &pm, err, base.st.h, false);
-        if (rc) return rc;
-        if (pp.st.type != pm.st.type) {
-            *err = "decomposition type changes within the difference step";
-            return NSLCT_E_NO_DECOMPOSITION;
-        }
-        for (int m = 0; m < 4; ++m)
-            for (int k = 0; k < 3; ++k) jac[(3 * m + k) * 10 + i] = (pp.st.mats[m][k] - pm.st.mats[m][k]) / (2 * h);
-    }
-    return NSLCT_OK;
+    return jacobian_followed(abcd, theta0, Nx, Ny, dx, dy, o, base.st.type == 0 ? 0 : base.st.type, base.st.h,
+                             h, jac, err);
 }
 
 int plan_theta_jacobian(const PlanData& p, double jac[12 * 10], std::string* err) {
@@ -987,11 +1206,14 @@ int plan_theta_jacobian(const PlanData& p, double jac[12 * 10], std::string* err
                "perturbed matrices; plan with nslct_plan_lie to differentiate";
         return NSLCT_E_UNSUPPORTED;
     }
-    nslct_opts o = p.opts;
-    // Closed-form stages (types 3-5) take a smaller difference step than the
-    // searched gauge, whose minimiser is resolved to about 1e-12.
+    // A searched gauge on a full kink set: the implicit-function derivative.
+    if (jacobian_implicit(p, jac)) return NSLCT_OK;
+    // Otherwise central differences of the planner, the gauge followed from
+    // the plan's own; closed-form stages (types 3-5) take a smaller step than
+    // a searched gauge, whose minimiser is resolved to about 1e-12.
     const double h = p.st.type >= 3 ? 1e-5 : 1e-4;
-    return plan_jacobian(p.abcd0, p.theta, p.Nx, p.Ny, p.st.dx, p.st.dy, o, h, jac, err);
+    return jacobian_followed(p.abcd0, p.theta, p.Nx, p.Ny, p.st.dx, p.st.dy, p.opts,
+                             p.st.type == 0 ? 0 : p.st.type, p.st.h, h, jac, err);
 }
 
 void theta_gradient(const double jac[12 * 10], const double gst[12], double out[10]) {

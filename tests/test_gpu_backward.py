@@ -167,8 +167,8 @@ def test_batch32_512_gradients(torch, ag):
 
 def test_backward_theta_without_theta_and_plan_jacobian(torch, ag):
     """nslct_backward_theta with grad_theta = NULL gives the same grad_x
-    bits; the plan's cached Jacobian equals nslct_plan_jacobian at the step
-    of its type."""
+    bits; the plan's cached Jacobian agrees with nslct_plan_jacobian's
+    re-solved central differences (step of its type) to their truncation."""
     import paper_1707_03688_amd as nl
     M0 = next(synth.symplectic_candidates(5))
     Nx, Ny, dx, dy = 64, 48, 0.45, 0.6
@@ -182,7 +182,8 @@ def test_backward_theta_without_theta_and_plan_jacobian(torch, ag):
     assert none is None and torch.equal(gx1, gx2) and np.all(np.isfinite(gt))
     typ = p.stages()["type"]
     ref = ag.plan_jacobian(M0, th, Nx, Ny, dx, dy, type_override=typ, h=1e-5 if typ >= 3 else 1e-4)
-    assert np.array_equal(p.theta_jacobian(), ref)
+    J = p.theta_jacobian()
+    assert np.max(np.abs(J - ref)) <= 1e-4 * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("override", [4, 5])
