@@ -106,7 +106,9 @@ typedef struct {
  * 2D CC; their overall constant is +1 like the two-CC chains' (the paper's
  * DFT constants taken literally would give -1 there), and their 1D CC uses
  * the unitary 1D DFT pair (a 1D CC with h = 0 is the identity).  They run as
- * three passes (48 B per sample for complex64) on the single-image path. */
+ * three passes (48 B per sample for complex64) on the single-image path at
+ * native lengths, and as their five-slot form (the same chain, a CC with a
+ * zero or rank-one matrix in place of the missing one) at other lengths. */
 typedef struct {
     int type;
     double mats[4][3];
@@ -178,7 +180,8 @@ int nslct_launch_pass(nslct_plan_t plan, int direction, int pass, int count,
                       const void* in, void* out, void* stream);
 
 /* Number of passes of the single-image path of `plan`: 3 for the reduced
- * chains (types 3-5) in complex64 / complex128, else 5.  Host only. */
+ * chains (types 3-5) in complex64 / complex128 at native lengths (2^k,
+ * 3 * 2^k), else 5.  Host only. */
 int nslct_plan_passes(nslct_plan_t plan, int* npasses);
 
 /* Ragged batch: `count` plans (each with its own matrix and size) over one

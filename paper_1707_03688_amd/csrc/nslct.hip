@@ -556,10 +556,13 @@ hipError_t launch_pass_typed(const PlanData& d, int dir, int pass, int count, co
 }
 
 // Passes of the single-image path: the three-pass schedule of a reduced
-// chain (CM-CC-CM, LC) in c64 / c128, else the five-pass chain.
+// chain (CM-CC-CM, LC) in c64 / c128 at native line lengths, else the
+// five-pass chain (for a reduced chain its five-slot form, which the
+// Bluestein pass kernels run at any length).
 int plan_passes(const PlanData& d) {
     const bool split = d.precision == NSLCT_C64_SPLIT_F16 || d.precision == NSLCT_C64_SPLIT_BF16;
-    return (!split && d.prog[0].npass > 0) ? d.prog[0].npass : 5;
+    const bool native = native_line(d.Nx) && native_line(d.Ny);
+    return (!split && native && d.prog[0].npass > 0) ? d.prog[0].npass : 5;
 }
 
 template <typename T>

@@ -398,3 +398,14 @@ def test_planner_cross_check_2000_draws(nl):
                 assert f <= ref.f * (1 + 1e-8) and ref.f <= f * (1 + 1e-8)
             checked += 1
     assert n == 2000 and checked >= 1900
+
+
+def test_reduced_types_at_bluestein_lengths_use_five_passes(nl):
+    """Reduced chains (CM-CC-CM, LC) run three passes at native lengths and
+    their five-slot form at other lengths."""
+    FT = np.block([[np.zeros((2, 2)), np.eye(2)], [-np.eye(2), np.zeros((2, 2))]])
+    assert nl.Plan(FT, 64, 48).passes() == 3
+    assert nl.Plan(FT, 65, 48).passes() == 5
+    M = next(synth.symplectic_candidates(11))
+    p = nl.Plan(M, 100, 100, 0.25, 0.25, type_override=6)
+    assert p.stages()["type"] in (4, 5) and p.passes() == 5

@@ -89,3 +89,52 @@ def test_additivity(torch, nl, which):
     assert nmse == pytest.approx(oracle_nmse, rel=1e-6)
     # The larger grid is well below the printed unpadded values (3.6e-5, 0.052).
     assert nmse < (1e-6 if which == "g1" else 1e-3), nmse
+
+
+@pytest.fixture(scope="module")
+def g2_truth():
+    """The direct method (eq. Intro32) for g2 / M2 on the 165 x 165 output
+    grid from the 0.078-spacing input (Sec. 5.1): about a minute of host time."""
+    pv = printed_values()
+    M = symplectic.project(paper_matrices()["M2"])
+    df = pv["truth_spacing"]
+    Nf = 2 * int(10.5 / df) + 1
+    gf = synth.hg_signal([(2, 18), (14, 11)], Nf, df)
+    return M, direct.direct(M, gf, df, df, 165, 165, 0.2, 0.2)
+
+
+def test_zero_padding_sweep_g2(torch, nl, g2_truth):
+    """Sec. 5.1 (Fig. 3): g2 on the 165 x 165 grid (spacing 0.2), zero-padded
+    to 165 + dN for dN = 0, 10, ..., 50 (Bluestein line DFTs), transformed by
+    the HA-NsDLCT (eq. HA28 form) and the LC-NsDLCT (eq. LC12, the smaller
+    eq. HA24 objective) of M2, cropped to the central 165 x 165 and compared
+    with the direct method.  HA at dN = 0 gives the printed 1.1e-3 (within a
+    factor 3); padding lowers both curves; every GPU output equals the oracle
+    chain at the planner's stages to 1e-11."""
+    from oracle import fast
+    M, T = g2_truth
+    N, d = 165, 0.2
+    g = synth.hg_signal([(2, 18), (14, 11)], N, d)
+    curves = {"HA": [], "LC": []}
+    for dN in (0, 10, 20, 30, 40, 50):
+        Np = N + dN
+        o = Np // 2 - N // 2
+        gp = np.zeros((Np, Np), dtype=np.complex128)
+        gp[o:o + N, o:o + N] = g
+        for name, typ in (("HA", 1), ("LC", 6)):
+            p, G = _gpu(nl, torch, M, gp, d, typ=typ)
+            st = p.stages()
+            if st["type"] in (4, 5):
+                axis = st["type"] - 4
+                ref = fast.forward(fast.lc_plan(M, Np, Np, d, d, axis=axis), gp)
+            else:
+                ref = chain.forward(oplan.plan_from_stages(st["type"], st["mats"], Np, Np, d, d), gp)
+            if dN in (0, 30):
+                assert chain.rel_l2(G, ref) <= 1e-11
+            Gc = G[o:o + N, o:o + N]
+            curves[name].append(min(chain.rel_l2(Gc, T), chain.rel_l2(Gc, -T)) ** 2)
+    print("NMSE_acc g2 / M2 vs dN = 0..50:", {k: [f"{v:.2e}" for v in vs] for k, vs in curves.items()})
+    pv = printed_values()
+    assert pv["nmse_acc_ha_g2"] / 3 <= curves["HA"][0] <= pv["nmse_acc_ha_g2"] * 3
+    for name in curves:
+        assert curves[name][-1] < curves[name][0] / 10, (name, curves[name])

@@ -159,3 +159,23 @@ def test_batched_and_split_paths_accept_reduced_types(torch, nl):
         ref = p.forward(xi)
         got = ps.forward(xi)
         assert (torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref)).item() <= 1e-4
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+@pytest.mark.parametrize("typ", [3, 4, 5])
+def test_reduced_chains_at_bluestein_lengths(torch, nl, typ, precision):
+    """At lengths without a native line FFT (here 100 x 75) the reduced
+    chains run their five-slot form through the Bluestein line DFTs: forward
+    and inverse against the oracle's reduced chains."""
+    Nx, Ny = 100, 75
+    d = math.sqrt(2 * math.pi / 100)
+    M = _cmccm_matrix(71) if typ == 3 else _lc_matrix(72)
+    po = _oracle_plan(typ, M, Nx, Ny, d)
+    p = nl.Plan(M, Nx, Ny, d, d, precision=precision, type_override=typ)
+    assert p.stages()["type"] == typ and p.passes() == 5
+    g = synth.complex_normal((Nx, Ny), seed=73)
+    dt = torch.complex64 if precision == "c64" else torch.complex128
+    x = torch.from_numpy(g).to(dt).cuda()
+    tol = 1e-5 if precision == "c64" else 1e-11
+    assert chain.rel_l2(p.forward(x).cpu().numpy(), fast.forward(po, g)) <= tol
+    assert chain.rel_l2(p.inverse(x).cpu().numpy(), fast.inverse(po, g)) <= tol
