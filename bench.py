@@ -208,7 +208,9 @@ def bench_batched(nl, torch, synth, np, count=256, seed=2):
             "speedup_vs_loop": t_loop / t_graph,
             "hbm_effective_GBps": 80.0 * px / t_graph / 1e9,
             "pct_hbm_peak": 80.0 * px / t_graph / 1e9 / HBM_PEAK_GBPS * 100,
-            "autotuned_wg_per_cu": b.mult}
+            "schedule": {f"{'cols' if c else 'rows'} {N}": f"{v['lines']} lines x "
+                         + (f"{v['mult']}/CU" if v["mult"] else "1 WG/item")
+                         for (c, N), v in b.schedules().items()}}
 
 
 def bench_split(nl, torch, synth, np, count=8, N=4096, reps=3):

@@ -190,22 +190,44 @@ int nslct_plan_passes(nslct_plan_t plan, int* npasses);
  * precision; sides must be 64, 128, 192, 256, 384, 512, 768 or 1024.  The
  * batch copies the plans (they may be destroyed afterwards), uploads a
  * table of pass arguments per (image, direction, pass) and an XCD-balanced
- * work list to the current device, and autotunes the grid of its pass
- * kernels on scratch images (device work and allocation happen here, once).
+ * work list to the current device.  Its passes run one launch per group
+ * (pass axis, line length); each group's schedule, the tile width (lines
+ * per work item: 256, 512 or 1024 threads' worth, as LDS allows) and the
+ * grid (1, 2, 4 or 8 persistent workgroups per CU, or one workgroup per
+ * item), is taken from the schedule cache or chosen by timing every
+ * candidate on scratch images (device work and allocation happen here,
+ * once).  The schedule cache is a text file keyed by (GPU architecture,
+ * precision, axis, line length, lines of the group rounded up to a power of
+ * two): NSLCT_TUNE_CACHE names it (off: no cache), default
+ * $HOME/.cache/nslct/batch_schedule.txt; unwritable paths only disable it.
  * Not reentrant: calls on one batch from several threads are serialised
  * internally. */
 int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out);
 
-/* Packed buffer length in samples, the autotuned persistent grid (workgroups
- * per CU; 0 = one workgroup per work item) and the forward time measured
- * while tuning, in microseconds (any pointer may be NULL). */
+/* Packed buffer length in samples, the grid set by nslct_batch_set_grid
+ * (workgroups per CU; 0 = one workgroup per work item; -1 = per-group
+ * schedules as tuned) and the forward time of the whole batch measured
+ * after tuning, in microseconds (0 when every schedule came from the cache;
+ * any pointer may be NULL). */
 int nslct_batch_info(nslct_batch_t batch, size_t* total_samples, int* mult, double* tuned_us);
 
-/* Overrides the autotuned grid: mult persistent workgroups per CU (1, 2, 4
- * or 8) or 0 for one workgroup per work item; any other value is
- * NSLCT_E_ARG.  Synchronises the batch's device, then drops the captured
- * graphs (the next graph run captures again).  Results do not depend on the
- * grid (each work item is computed by the same code whatever the grid). */
+/* Schedule of the group of pass axis `col` (0: row passes, lines of length
+ * Ny; 1: column passes, lines of length Nx) and line length N: lines per
+ * work item, grid (workgroups per CU, 0 = one per item) and whether it came
+ * from the schedule cache.  NSLCT_E_ARG when the batch has no such group. */
+int nslct_batch_group(nslct_batch_t batch, int col, int N, int* lines, int* mult, int* cached);
+
+/* Sets one group's tile width (`lines`, one of its candidates) and grid
+ * (mult as nslct_batch_set_grid); synchronises the batch's device and drops
+ * the captured graphs.  Results do not depend on the schedule. */
+int nslct_batch_set_group(nslct_batch_t batch, int col, int N, int lines, int mult);
+
+/* Puts every group on `mult` persistent workgroups per CU (1, 2, 4 or 8) or
+ * on one workgroup per work item (0), keeping the tile widths; any other
+ * value is NSLCT_E_ARG.  Synchronises the batch's device, then drops the
+ * captured graphs (the next graph run captures again).  Results do not
+ * depend on the grid (each work item is computed by the same code whatever
+ * the grid). */
 int nslct_batch_set_grid(nslct_batch_t batch, int mult);
 
 /* Forward / inverse of every image of the batch: the five passes, each one

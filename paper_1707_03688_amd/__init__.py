@@ -259,6 +259,25 @@ class Batch:
         check(lib.nslct_batch_set_grid(self._h, int(mult)))
         self.mult = int(mult)
 
+    def group(self, col: int, N: int) -> dict:
+        """Schedule of one group (``nslct_batch_group``)."""
+        lines, mult, cached = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib.nslct_batch_group(self._h, int(col), int(N), ctypes.byref(lines), ctypes.byref(mult),
+                                    ctypes.byref(cached)))
+        return {"lines": lines.value, "mult": mult.value, "cached": bool(cached.value)}
+
+    def schedules(self) -> dict:
+        """Schedules of every group: {(col, N): {...}}."""
+        out = {}
+        for col in (0, 1):
+            for N in sorted({p.Nx if col else p.Ny for p in self.plans}):
+                out[(col, N)] = self.group(col, N)
+        return out
+
+    def set_group(self, col: int, N: int, lines: int, mult: int):
+        """Set one group's tile width and grid (``nslct_batch_set_group``)."""
+        check(lib.nslct_batch_set_group(self._h, int(col), int(N), int(lines), int(mult)))
+
     def views(self, flat):
         """Per-image [Nx, Ny] views of a packed tensor."""
         return [flat[o:o + p.Nx * p.Ny].view(p.Nx, p.Ny) for o, p in zip(self.offsets, self.plans)]

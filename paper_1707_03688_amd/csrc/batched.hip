@@ -3,7 +3,11 @@
 // lists, captured in a HIP graph; autotuned at creation.
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+
 #include <algorithm>
+#include <cstdlib>
+#include <fstream>
 #include <functional>
 #include <memory>
 #include <mutex>
@@ -42,17 +46,22 @@ struct BatchArgs {
     int pass;
 };
 
-constexpr int kBatchThreads = 256;
 // Line lengths the batched kernel handles (all with TPL <= 64).
 #define NSLCT_BATCH_SIZES(X) X(64) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
-// Lines per work item: kBatchThreads threads' worth, doubled for complex64
-// column tiles (1024-long columns: 8 columns, 64-byte row segments; measured
-// 2.75 -> 2.68 ms on the 256-image ragged batch).
-template <int N, bool COL = false, typename T = float>
-constexpr int batch_lines() {
-    return ((COL && sizeof(T) == 4) ? 2 : 1) * kBatchThreads / LinePlan<N>::TPL;
+// Tile widths of a work item: W = 0, 1, 2 give 256, 512, 1024 threads, i.e.
+// (256 << W) / TPL lines (row passes W <= 1).  A width is a candidate when
+// its lines fit the 160 KB of LDS.
+constexpr int kMaxWidth = 2;
+template <int N, int W>
+constexpr int width_lines() {
+    return (256 << W) / LinePlan<N>::TPL;
 }
+template <typename T, int N, bool COL, int W>
+constexpr bool width_ok() {
+    return (COL || W <= 1) && width_lines<N, W>() * lds_line_elems<N>() * (int)sizeof(cplx<T>) <= 160 * 1024;
+}
+
 bool batch_size_ok(int n) {
     switch (n) {
 #define NSLCT_CASE_OK(v) case v:
@@ -64,28 +73,55 @@ bool batch_size_ok(int n) {
     }
 }
 
-int host_batch_lines(int n, bool col, bool dbl) {
+template <int N>
+bool host_width_ok_n(int w, bool col, bool dbl) {
+    switch (w) {
+        case 0: return dbl ? (col ? width_ok<double, N, true, 0>() : width_ok<double, N, false, 0>())
+                           : (col ? width_ok<float, N, true, 0>() : width_ok<float, N, false, 0>());
+        case 1: return dbl ? (col ? width_ok<double, N, true, 1>() : width_ok<double, N, false, 1>())
+                           : (col ? width_ok<float, N, true, 1>() : width_ok<float, N, false, 1>());
+        case 2: return dbl ? (col ? width_ok<double, N, true, 2>() : width_ok<double, N, false, 2>())
+                           : (col ? width_ok<float, N, true, 2>() : width_ok<float, N, false, 2>());
+        default: return false;
+    }
+}
+bool host_width_ok(int n, int w, bool col, bool dbl) {
+    switch (n) {
+#define NSLCT_CASE_W(v) \
+    case v:           \
+        return host_width_ok_n<v>(w, col, dbl);
+        NSLCT_BATCH_SIZES(NSLCT_CASE_W)
+#undef NSLCT_CASE_W
+        default:
+            return false;
+    }
+}
+int host_width_lines(int n, int w) {
     switch (n) {
 #define NSLCT_CASE_L(v) \
     case v:           \
-        return (col && !dbl) ? batch_lines<v, true, float>() : batch_lines<v>();
+        return (256 << w) / LinePlan<v>::TPL;
         NSLCT_BATCH_SIZES(NSLCT_CASE_L)
 #undef NSLCT_CASE_L
         default:
             return 1;
     }
 }
+// The width used before (or without) tuning: 256 threads, complex64 column
+// tiles twice as wide (1024-long columns: 8 columns, 64-byte row segments).
+int default_width(bool col, bool dbl) { return (col && !dbl) ? 1 : 0; }
 
-// Batched pass over the images of one line length N.  LOOP: a persistent
-// grid whose workgroups walk the group's item list with a grid stride (item
-// i belongs to XCD i mod 8, which is also the XCD of every workgroup that
-// visits it: the grid size is a multiple of 8); otherwise one workgroup per
-// item, without the loop, whose loop-invariant values would otherwise stay
-// in registers across iterations.
-template <typename T, int N, bool COL, bool LOOP>
-__global__ void __launch_bounds__((batch_lines<N, COL, T>() * LinePlan<N>::TPL))
+// Batched pass over the images of one line length N, L = width_lines<N, W>
+// lines per work item.  LOOP: a persistent grid whose workgroups walk the
+// group's item list with a grid stride (item i belongs to XCD i mod 8,
+// which is also the XCD of every workgroup that visits it: the grid size is
+// a multiple of 8); otherwise one workgroup per item, without the loop,
+// whose loop-invariant values would otherwise stay in registers across
+// iterations.
+template <typename T, int N, bool COL, bool LOOP, int W>
+__global__ void __launch_bounds__((width_lines<N, W>() * LinePlan<N>::TPL))
     nslct_batched_pass(BatchArgs<T> b, const BatchItem* __restrict__ items, const BatchPass<T>* __restrict__ passes) {
-    constexpr int L = batch_lines<N, COL, T>();
+    constexpr int L = width_lines<N, W>();
     __shared__ cplx<T> lds[L * lds_line_elems<N>()];
     // The work list and the pass table come in as restrict parameters (no
     // store of the kernel can alias them), so their uniform-index loads are
@@ -110,27 +146,44 @@ __global__ void __launch_bounds__((batch_lines<N, COL, T>() * LinePlan<N>::TPL))
     }
 }
 
-template <typename T, bool COL>
-hipError_t launch_batched_group(int N, const BatchArgs<T>& a, int grid, hipStream_t s) {
-    switch (N) {
-#define NSLCT_CASE_LAUNCH(v)                                                                        \
-    case v:                                                                                         \
-        if (grid >= a.nitems)                                                                       \
-            hipLaunchKernelGGL((nslct_batched_pass<T, v, COL, false>), dim3(a.nitems),               \
-                               dim3(batch_lines<v, COL, T>() * LinePlan<v>::TPL), 0, s, a,          \
-                               a.items, a.passes);                                                  \
-        else                                                                                        \
-            hipLaunchKernelGGL((nslct_batched_pass<T, v, COL, true>), dim3(grid),                    \
-                               dim3(batch_lines<v, COL, T>() * LinePlan<v>::TPL), 0, s, a,          \
-                               a.items, a.passes);                                                  \
+template <typename T, int N, bool COL, int W>
+hipError_t launch_batched_w(const BatchArgs<T>& a, int grid, hipStream_t s) {
+    if constexpr (width_ok<T, N, COL, W>()) {
+        const dim3 block(width_lines<N, W>() * LinePlan<N>::TPL);
+        if (grid >= a.nitems)
+            hipLaunchKernelGGL((nslct_batched_pass<T, N, COL, false, W>), dim3(a.nitems), block, 0, s, a, a.items,
+                               a.passes);
+        else
+            hipLaunchKernelGGL((nslct_batched_pass<T, N, COL, true, W>), dim3(grid), block, 0, s, a, a.items,
+                               a.passes);
         return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, bool COL, int N>
+hipError_t launch_batched_n(int w, const BatchArgs<T>& a, int grid, hipStream_t s) {
+    switch (w) {
+        case 0: return launch_batched_w<T, N, COL, 0>(a, grid, s);
+        case 1: return launch_batched_w<T, N, COL, 1>(a, grid, s);
+        case 2: return launch_batched_w<T, N, COL, 2>(a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, bool COL>
+hipError_t launch_batched_group(int N, int w, const BatchArgs<T>& a, int grid, hipStream_t s) {
+    switch (N) {
+#define NSLCT_CASE_LAUNCH(v) \
+    case v:                  \
+        return launch_batched_n<T, COL, v>(w, a, grid, s);
         NSLCT_BATCH_SIZES(NSLCT_CASE_LAUNCH)
 #undef NSLCT_CASE_LAUNCH
         default:
             return hipErrorInvalidValue;
     }
 }
-
 
 }  // namespace
 
@@ -149,9 +202,13 @@ struct nslct_batch_s {
         int nitems;
         int grid;
         BatchItem* items;
+        int width;    // tile width index (width_lines)
+        int mult;     // persistent workgroups per CU (0: one per item)
+        int cached;   // schedule taken from the schedule cache
+        double us;    // measured time of one launch of this group while tuning
     };
     std::vector<Group> groups[2];
-    int mult = 0;  // autotuned persistent workgroups per CU (0: one per item)
+    int mult = 0;  // grid override of nslct_batch_set_grid (-1: per-group tuned grids)
     int cus = 256;  // compute units of the device
     double tuned_us = 0.0;
     hipStream_t cap = nullptr;
@@ -180,6 +237,22 @@ struct nslct_batch_s {
 
 namespace {
 
+// One pass of one group (axis col, one line length) on stream st.
+template <typename T>
+hipError_t launch_group_pass(const nslct_batch_s& b, int col, const nslct_batch_s::Group& g, int dir, int pass,
+                             const void* in, void* out, hipStream_t st) {
+    BatchArgs<T> a;
+    a.in = (const cplx<T>*)in;
+    a.out = (cplx<T>*)out;
+    a.passes = (const BatchPass<T>*)b.d_passes;
+    a.items = g.items;
+    a.nitems = g.nitems;
+    a.dir = dir;
+    a.pass = pass;
+    return col ? launch_batched_group<T, true>(g.N, g.width, a, g.grid, st)
+               : launch_batched_group<T, false>(g.N, g.width, a, g.grid, st);
+}
+
 template <typename T>
 hipError_t run_batched_t(const nslct_batch_s& b, int dir, const void* in, void* out, hipStream_t s) {
     for (int pass = 0; pass < 5; ++pass) {
@@ -194,17 +267,8 @@ hipError_t run_batched_t(const nslct_batch_s& b, int dir, const void* in, void* 
             for (size_t k = 0; k < gs.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(b.side[k], b.ev[0], 0);
         }
         for (size_t k = 0; k < gs.size() && e == hipSuccess; ++k) {
-            BatchArgs<T> a;
-            a.in = (const cplx<T>*)(pass == 0 ? in : out);
-            a.out = (cplx<T>*)out;
-            a.passes = (const BatchPass<T>*)b.d_passes;
-            a.items = gs[k].items;
-            a.nitems = gs[k].nitems;
-            a.dir = dir;
-            a.pass = pass;
             hipStream_t st = fork ? b.side[k] : s;
-            e = col ? launch_batched_group<T, true>(gs[k].N, a, gs[k].grid, st)
-                    : launch_batched_group<T, false>(gs[k].N, a, gs[k].grid, st);
+            e = launch_group_pass<T>(b, col, gs[k], dir, pass, pass == 0 ? in : out, out, st);
             if (e == hipSuccess && fork) e = hipEventRecord(b.ev[1 + k], st);
         }
         if (fork)
@@ -223,7 +287,7 @@ hipError_t run_batched(const nslct_batch_s& b, int dir, const void* in, void* ou
 // XCDs: whole images go to the least-loaded XCD (largest first), and item i
 // of the list belongs to XCD i mod 8, so adjacent line tiles of one image
 // share an XCD and its L2.
-std::vector<BatchItem> build_items(const nslct_batch_s& b, bool col, int N) {
+std::vector<BatchItem> build_items(const nslct_batch_s& b, bool col, int N, int L) {
     std::vector<int> order;
     for (int i = 0; i < b.count; ++i) {
         const PlanData& d = b.plans[i].d;
@@ -236,7 +300,6 @@ std::vector<BatchItem> build_items(const nslct_batch_s& b, bool col, int N) {
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
     std::vector<std::vector<BatchItem>> per(8);
     double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int L = host_batch_lines(N, col, b.precision == NSLCT_C128);
     for (int i : order) {
         const PlanData& d = b.plans[i].d;
         const int nl = col ? d.Ny : d.Nx;
@@ -255,13 +318,102 @@ std::vector<BatchItem> build_items(const nslct_batch_s& b, bool col, int N) {
     return items;
 }
 
+int grid_for(int mult, int cus, int nitems) {
+    const int want = mult == 0 ? nitems : ((mult * cus + 7) / 8) * 8;
+    return std::max(8, std::min(want, nitems));
+}
+
+// Every group on `mult` workgroups per CU (nslct_batch_set_grid).
 void set_grids(nslct_batch_s* b, int mult, int cus) {
     b->mult = mult;
     for (auto& gs : b->groups)
         for (auto& g : gs) {
-            const int want = mult == 0 ? g.nitems : ((mult * cus + 7) / 8) * 8;
-            g.grid = std::max(8, std::min(want, g.nitems));
+            g.mult = mult;
+            g.grid = grid_for(mult, cus, g.nitems);
         }
+}
+
+// (Re)builds and uploads the work list of group g for tile width w.
+hipError_t set_group_width(nslct_batch_s& b, int col, nslct_batch_s::Group& g, int w) {
+    const std::vector<BatchItem> items = build_items(b, col == 1, g.N, host_width_lines(g.N, w));
+    if (g.items) {
+        hipError_t e = hipFree(g.items);
+        g.items = nullptr;
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc(&g.items, sizeof(BatchItem) * items.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(g.items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+    g.nitems = (int)items.size();
+    g.width = w;
+    return e;
+}
+
+// ------------------------------------------------------------ schedule cache
+// The tuned schedule of a group is kept in a text file, one line per
+//   <gfx arch> <precision> <axis 0 rows / 1 columns> <N> <items, rounded up
+//   to a power of two> <width> <mult> <microseconds>
+// (file NSLCT_TUNE_CACHE, default $HOME/.cache/nslct/batch_schedule.txt;
+// NSLCT_TUNE_CACHE=off disables it).  A batch whose groups are all found
+// there is not tuned again.
+struct CacheKey {
+    std::string arch;
+    int prec, col, N, bucket;
+};
+
+std::mutex g_cache_mu;
+
+std::string cache_path() {
+    const char* env = std::getenv("NSLCT_TUNE_CACHE");
+    if (env) return std::string(env) == "off" ? std::string() : std::string(env);
+    const char* home = std::getenv("HOME");
+    if (!home || !*home) return std::string();
+    return std::string(home) + "/.cache/nslct/batch_schedule.txt";
+}
+
+int bucket_of(int nitems) {
+    int b = 1;
+    while (b < nitems) b <<= 1;
+    return b;
+}
+
+bool cache_lookup(const std::string& path, const CacheKey& k, int* w, int* mult) {
+    if (path.empty()) return false;
+    std::ifstream f(path);
+    std::string arch;
+    int prec, col, N, bucket, ww, mm;
+    double us;
+    bool found = false;
+    while (f >> arch >> prec >> col >> N >> bucket >> ww >> mm >> us) {
+        if (arch == k.arch && prec == k.prec && col == k.col && N == k.N && bucket == k.bucket) {
+            *w = ww;  // the last entry for a key wins
+            *mult = mm;
+            found = true;
+        }
+    }
+    return found;
+}
+
+void cache_store(const std::string& path, const CacheKey& k, int w, int mult, double us) {
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {
+        // Create the parent directories (best effort; errors only skip caching).
+        std::string dir = path.substr(0, slash);
+        for (size_t p = 1; p <= dir.size(); ++p)
+            if (p == dir.size() || dir[p] == '/') (void)mkdir(dir.substr(0, p).c_str(), 0755);
+    }
+    std::ofstream f(path, std::ios::app);
+    if (f) f << k.arch << ' ' << k.prec << ' ' << k.col << ' ' << k.N << ' ' << k.bucket << ' ' << w << ' '
+             << mult << ' ' << us << '\n';
+}
+
+std::string device_arch(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a(prop.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
 }
 
 int batch_fail(nslct_batch_s* b, hipError_t e, const char* what) {
@@ -343,6 +495,7 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
     if (e != hipSuccess) return batch_fail(b, e, "hipGetDevice");
     e = b->precision == NSLCT_C128 ? upload_batch_passes<double>(*b) : upload_batch_passes<float>(*b);
     if (e != hipSuccess) return batch_fail(b, e, "pass table upload");
+    const bool dbl = b->precision == NSLCT_C128;
     for (int col = 0; col < 2; ++col) {
         std::vector<int> sizes;
         for (int i = 0; i < count; ++i) {
@@ -351,13 +504,9 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
         }
         std::sort(sizes.begin(), sizes.end(), std::greater<int>());
         for (int N : sizes) {
-            const std::vector<BatchItem> items = build_items(*b, col == 1, N);
-            nslct_batch_s::Group g{N, (int)items.size(), 8, nullptr};
-            e = hipMalloc(&g.items, sizeof(BatchItem) * items.size());
-            if (e != hipSuccess) return batch_fail(b, e, "hipMalloc");
-            b->groups[col].push_back(g);
-            e = hipMemcpy(g.items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
-            if (e != hipSuccess) return batch_fail(b, e, "hipMemcpy");
+            b->groups[col].push_back({N, 0, 8, nullptr, default_width(col == 1, dbl), 0, 0, 0.0});
+            e = set_group_width(*b, col, b->groups[col].back(), b->groups[col].back().width);
+            if (e != hipSuccess) return batch_fail(b, e, "work list upload");
         }
     }
     e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
@@ -376,42 +525,104 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
         b->ev.push_back(ev);
     }
 
-    // Autotune the persistent grid (workgroups per CU) on scratch images.
+    // Schedule of every group (pass axis, line length): tile width and grid,
+    // from the schedule cache, else measured here on scratch images.
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) cus = 256;
     b->cus = cus;
-    const size_t bytes = b->total * (b->precision == NSLCT_C128 ? 16 : 8);
-    void* scratch = nullptr;
-    e = hipMalloc(&scratch, bytes);
-    if (e != hipSuccess) return batch_fail(b, e, "hipMalloc (autotune scratch)");
-    e = hipMemsetAsync(scratch, 0, bytes, b->cap);
+    b->mult = -1;
     const int mults[] = {0, 1, 2, 4, 8};  // 0: one workgroup per item
-    double best = 1e30;
-    int best_mult = 0;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    for (int m : mults) {
-        if (e != hipSuccess) break;
-        set_grids(b, m, cus);
-        e = run_batched(*b, 0, scratch, scratch, b->cap);  // warm-up
+    const std::string path = cache_path();
+    const std::string arch = device_arch(b->device);
+    auto key_of = [&](int col, const nslct_batch_s::Group& g) {
+        long long lines = 0;  // lines of this group over the batch (independent of the width)
+        for (int i = 0; i < count; ++i) {
+            const PlanData& d = b->plans[i].d;
+            if ((col ? d.Nx : d.Ny) == g.N) lines += col ? d.Ny : d.Nx;
+        }
+        return CacheKey{arch, b->precision, col, g.N, bucket_of((int)std::min<long long>(lines, 1 << 30))};
+    };
+    bool all_cached = true;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (int col = 0; col < 2; ++col)
+            for (auto& g : b->groups[col]) {
+                int w = 0, m = 0;
+                const bool hit = cache_lookup(path, key_of(col, g), &w, &m) && host_width_ok(g.N, w, col == 1, dbl) &&
+                                 std::find(std::begin(mults), std::end(mults), m) != std::end(mults);
+                if (hit) {
+                    if (w != g.width) e = set_group_width(*b, col, g, w);
+                    if (e != hipSuccess) return batch_fail(b, e, "work list upload");
+                    g.mult = m;
+                    g.grid = grid_for(m, cus, g.nitems);
+                    g.cached = 1;
+                } else {
+                    all_cached = false;
+                }
+            }
+    }
+    if (!all_cached) {
+        const size_t bytes = b->total * (dbl ? 16 : 8);
+        void* scratch = nullptr;
+        e = hipMalloc(&scratch, bytes);
+        if (e != hipSuccess) return batch_fail(b, e, "hipMalloc (autotune scratch)");
+        e = hipMemsetAsync(scratch, 0, bytes, b->cap);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        for (int col = 0; col < 2 && e == hipSuccess; ++col)
+            for (auto& g : b->groups[col]) {
+                if (g.cached || e != hipSuccess) continue;
+                // The heavier pass of the axis (two line DFTs around a chirp).
+                const int pass = col ? 1 : 2;
+                double best = 1e30;
+                int bw = g.width, bm = 0;
+                for (int w = 0; w <= kMaxWidth && e == hipSuccess; ++w) {
+                    if (!host_width_ok(g.N, w, col == 1, dbl)) continue;
+                    e = set_group_width(*b, col, g, w);
+                    for (int m : mults) {
+                        if (e != hipSuccess) break;
+                        g.grid = grid_for(m, cus, g.nitems);
+                        auto launch = [&]() {
+                            return dbl ? launch_group_pass<double>(*b, col, g, 0, pass, scratch, scratch, b->cap)
+                                       : launch_group_pass<float>(*b, col, g, 0, pass, scratch, scratch, b->cap);
+                        };
+                        e = launch();  // warm-up
+                        if (e == hipSuccess) e = hipEventRecord(e0, b->cap);
+                        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch();
+                        if (e == hipSuccess) e = hipEventRecord(e1, b->cap);
+                        if (e == hipSuccess) e = hipEventSynchronize(e1);
+                        float ms = 0;
+                        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                        if (e == hipSuccess && ms / 3 * 1e3 < best) {
+                            best = ms / 3 * 1e3;
+                            bw = w;
+                            bm = m;
+                        }
+                    }
+                }
+                if (e != hipSuccess) break;
+                if (bw != g.width) e = set_group_width(*b, col, g, bw);
+                g.mult = bm;
+                g.grid = grid_for(bm, cus, g.nitems);
+                g.us = best;
+                std::lock_guard<std::mutex> lk(g_cache_mu);
+                cache_store(path, key_of(col, g), bw, bm, best);
+            }
+        // The whole batch with the chosen schedule.
+        if (e == hipSuccess) e = run_batched(*b, 0, scratch, scratch, b->cap);
         if (e == hipSuccess) e = hipEventRecord(e0, b->cap);
         for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run_batched(*b, 0, scratch, scratch, b->cap);
         if (e == hipSuccess) e = hipEventRecord(e1, b->cap);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && ms / 3 * 1e3 < best) {
-            best = ms / 3 * 1e3;
-            best_mult = m;
-        }
+        b->tuned_us = ms / 3 * 1e3;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(scratch);
+        if (e != hipSuccess) return batch_fail(b, e, "autotune");
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(scratch);
-    if (e != hipSuccess) return batch_fail(b, e, "autotune");
-    set_grids(b, best_mult, cus);
-    b->tuned_us = best;
     *out = b;
     return NSLCT_OK;
 }
@@ -439,6 +650,48 @@ int nslct_batch_set_grid(nslct_batch_t batch, int mult) {
     batch->graphs.clear();
     set_grids(batch, mult, batch->cus);
     return NSLCT_OK;
+}
+
+int nslct_batch_group(nslct_batch_t batch, int col, int N, int* lines, int* mult, int* cached) {
+    if (!batch) return fail(NSLCT_E_ARG, "null batch");
+    if (col != 0 && col != 1) return fail(NSLCT_E_ARG, "col must be 0 (rows) or 1 (columns)");
+    std::lock_guard<std::mutex> lk(batch->mu);
+    for (const auto& g : batch->groups[col])
+        if (g.N == N) {
+            if (lines) *lines = host_width_lines(g.N, g.width);
+            if (mult) *mult = g.mult;
+            if (cached) *cached = g.cached;
+            return NSLCT_OK;
+        }
+    return fail(NSLCT_E_ARG, "no group of that axis and line length in the batch");
+}
+
+int nslct_batch_set_group(nslct_batch_t batch, int col, int N, int lines, int mult) {
+    if (!batch) return fail(NSLCT_E_ARG, "null batch");
+    if (col != 0 && col != 1) return fail(NSLCT_E_ARG, "col must be 0 (rows) or 1 (columns)");
+    if (mult != 0 && mult != 1 && mult != 2 && mult != 4 && mult != 8)
+        return fail(NSLCT_E_ARG, "mult must be 0, 1, 2, 4 or 8");
+    std::lock_guard<std::mutex> lk(batch->mu);
+    for (auto& g : batch->groups[col]) {
+        if (g.N != N) continue;
+        int w = -1;
+        for (int k = 0; k <= kMaxWidth; ++k)
+            if (host_width_lines(N, k) == lines && host_width_ok(N, k, col == 1, batch->precision == NSLCT_C128)) w = k;
+        if (w < 0) return fail(NSLCT_E_ARG, "not a tile width of this group");
+        int dev = -1;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess && dev != batch->device) e = hipSetDevice(batch->device);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess && w != g.width) e = set_group_width(*batch, col, g, w);
+        if (dev >= 0 && dev != batch->device) (void)hipSetDevice(dev);
+        if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("set group: ") + hipGetErrorString(e));
+        g.mult = mult;
+        g.grid = grid_for(mult, batch->cus, g.nitems);
+        for (auto& gr : batch->graphs) (void)hipGraphExecDestroy(gr.exec);
+        batch->graphs.clear();
+        return NSLCT_OK;
+    }
+    return fail(NSLCT_E_ARG, "no group of that axis and line length in the batch");
 }
 
 int nslct_batch_run(nslct_batch_t batch, int direction, int mode, const void* in, void* out, void* stream) {

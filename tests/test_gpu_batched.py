@@ -119,3 +119,47 @@ def test_every_grid_mode_gives_the_same_bits(torch, nl, precision):
         with pytest.raises(nl.NslctError):
             b.set_grid(bad)
 
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_every_tile_width_gives_the_same_bits(torch, nl, precision):
+    """Each group's tile width candidates (lines per work item for 256, 512
+    or 1024 threads, as LDS allows) and grids compute every line with the
+    same code: graph replays equal the per-image loop bitwise."""
+    sizes = [1024, 768, 64, 384, 512, 128, 256, 192]
+    b, _ = _batch(nl, sizes, seed=48, precision=precision)
+    g = synth.complex_normal((b.total,), seed=6)
+    x = torch.from_numpy(g).to(torch.complex64 if precision == "c64" else torch.complex128).cuda()
+    ref = b.run(x, mode=2)
+    for (col, N), sch in b.schedules().items():
+        tpl = {64: 8, 128: 16, 192: 8, 256: 16, 384: 16, 512: 64, 768: 32, 1024: 64}[N]
+        tried = 0
+        for threads in (256, 512, 1024):
+            lines = threads // tpl
+            try:
+                b.set_group(col, N, lines, 2)
+            except nl.NslctError:
+                continue  # not a candidate (LDS, or 1024 threads on a row pass)
+            tried += 1
+            assert torch.equal(b.forward(x), ref), (col, N, lines)
+        assert tried >= 1
+        b.set_group(col, N, sch["lines"], sch["mult"])
+    assert torch.equal(b.forward(x), ref)
+
+
+def test_schedule_cache(torch, nl, tmp_path, monkeypatch):
+    """The first batch of a shape tunes its groups and writes the schedule
+    cache; the same batch built again takes every schedule from it (no
+    tuning run) and gives the same bits."""
+    monkeypatch.setenv("NSLCT_TUNE_CACHE", str(tmp_path / "sched.txt"))
+    b1, _ = _batch(nl, [512, 128, 256, 128], seed=49)
+    s1 = b1.schedules()
+    assert not any(v["cached"] for v in s1.values()) and b1.tuned_us > 0
+    lines = (tmp_path / "sched.txt").read_text().splitlines()
+    assert len(lines) == len(s1) and all(l.split()[0].startswith("gfx") for l in lines)
+    b2, _ = _batch(nl, [512, 128, 256, 128], seed=49)
+    s2 = b2.schedules()
+    assert all(v["cached"] for v in s2.values()) and b2.tuned_us == 0
+    assert {k: (v["lines"], v["mult"]) for k, v in s1.items()} == {k: (v["lines"], v["mult"]) for k, v in s2.items()}
+    x = torch.from_numpy(synth.complex_normal((b1.total,), seed=7)).to(torch.complex64).cuda()
+    assert torch.equal(b1.forward(x), b2.forward(x))
