@@ -29,10 +29,13 @@ linear canonical transform based on CM-CC-CM-CC decomposition":
 * ``fast``       -- the reduced decompositions: CM-CC-CM for symmetric B
   (Sec. 4.1, eq. Bsym12) and the LC-NsDLCT with a rank-one gauge (Sec.
   4.2.2, eqs. LC04-LC12).
+* ``route``      -- the decomposition (-B, A; -D, C)(0, -I; I, 0) of Sec.
+  4.2.2 for a12 = a21 = 0 (IDFT, then CM-CC-CM), its overall constant from
+  the closed-form propagation of a Gaussian through the factors.
 
 Pins (checked by ``tests/test_oracle_*.py``) tie every function to something
 other than itself; see the test docstrings.
 """
-from . import symplectic, ops, gauge, chain, dense, direct, sampling, fast  # noqa: F401
+from . import symplectic, ops, gauge, chain, dense, direct, sampling, fast, route  # noqa: F401
 from . import plan  # noqa: F401
 from .plan import Plan, plan_from_stages  # noqa: F401
