@@ -89,7 +89,12 @@ typedef struct {
                               3: CM-CC-CM (Sec. 4.1, B symmetric and invertible),
                               4: LC-NsDLCT with H = (h,0;0,0) (Sec. 4.2.2, eq. LC08),
                               5: LC-NsDLCT with H = (0,0;0,h) (eq. LC10),
-                              6: LC-NsDLCT, the form with the smaller eq. HA24 objective */
+                              6: LC-NsDLCT, the form with the smaller eq. HA24 objective; when neither
+                                 rank-one gauge exists, the route of 7 if it applies, else the HA-NsDLCT,
+                              7: for a12 = a21 = 0 (Sec. 4.2.2): (A, B; C, D) = (-B, A; -D, C)(0, -I; I, 0),
+                                 the IDFT then CM-CC-CM of (-B, A; -D, C) (eq. Bsym12); needs A
+                                 invertible and dx = sqrt(2 pi / Nx), dy = sqrt(2 pi / Ny) (the IDFT
+                                 keeps the grid only there), native lengths, complex64 / complex128 */
     double symplectic_tol; /* accepted max|M J M^T - J|, default 1e-9 */
     double det_min;        /* a middle CC matrix B' is accepted when |det B'| >= det_min * max(1, max|B_ij|^2)
                               (the invertibility conditions of eqs. Bsym08 and Bnonsym32), default 1e-6 */
@@ -102,6 +107,13 @@ typedef struct {
  *   type 3: mats = {P1, B, P3, 0}     -> CM(P1) CC(B) CM(P3)        (eq. Bsym12)
  *   type 4: mats = {P1, B', P3, H}, H = (h, 0; 0, 0), LC along x   (eq. LC12)
  *   type 5: mats = {P1, B', P3, H}, H = (0, 0; 0, h), LC along y
+ *   type 7: mats = {P1', A, P3', 0} of M' = (-B, A; -D, C):
+ *           G = j^phase_q CM(P1') CC(A) CM(P3') U^H g, with U^H the unitary
+ *           centred 2D IDFT and the CC unitary; phase_q makes the route the
+ *           operator of the CM-CC-CM-CC / CC-CM-CC-CM chain of M (the paper
+ *           leaves the constant of a product open; it is derived by
+ *           propagating a Gaussian through both factorisations in closed form).
+ *           Four passes (64 B per sample for complex64).
  * Each symmetric 2x2 matrix is stored as (x11, x12, x22).  Types 3-5 have one
  * 2D CC; their overall constant is +1 like the two-CC chains' (the paper's
  * DFT constants taken literally would give -1 there), and their 1D CC uses
@@ -117,6 +129,7 @@ typedef struct {
     double symplectic_residual;/* max|M J M^T - J| of the planned matrix */
     double dx, dy;             /* space sampling intervals */
     double dwx, dwy;           /* frequency intervals 2 pi / (N dx), 2 pi / (N dy) */
+    int phase_q;               /* type 7: overall constant j^phase_q (0..3); 0 otherwise */
 } nslct_stages;
 
 /* Fills *opts with the defaults. */

@@ -78,9 +78,10 @@ class Plan:
 
     @classmethod
     def from_stages(cls, typ: int, mats, Nx: int, Ny: int, dx: float, dy: float,
-                    precision: str = "c64") -> "Plan":
+                    precision: str = "c64", phase_q: int = 0) -> "Plan":
         st = Stages()
         st.type = int(typ)
+        st.phase_q = int(phase_q)
         for i, X in enumerate(mats):
             X = np.asarray(X, dtype=np.float64)
             st.mats[i][0] = X[0, 0]
@@ -114,7 +115,7 @@ class Plan:
             mats.append(np.array([[a, b], [b, c]]))
         return {"type": st.type, "mats": mats, "h": np.array(list(st.h)),
                 "f": st.gauge_objective, "residual": st.symplectic_residual,
-                "dx": st.dx, "dy": st.dy, "dwx": st.dwx, "dwy": st.dwy,
+                "dx": st.dx, "dy": st.dy, "dwx": st.dwx, "dwy": st.dwy, "phase_q": st.phase_q,
                 "Nx": getattr(self, "Nx", None), "Ny": getattr(self, "Ny", None)}
 
     def passes(self) -> int:

@@ -31,7 +31,8 @@ class Stages(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int), ("mats", (ctypes.c_double * 3) * 4),
                 ("h", ctypes.c_double * 3), ("gauge_objective", ctypes.c_double),
                 ("symplectic_residual", ctypes.c_double), ("dx", ctypes.c_double),
-                ("dy", ctypes.c_double), ("dwx", ctypes.c_double), ("dwy", ctypes.c_double)]
+                ("dy", ctypes.c_double), ("dwx", ctypes.c_double), ("dwy", ctypes.c_double),
+                ("phase_q", ctypes.c_int)]
 
 
 def _load():

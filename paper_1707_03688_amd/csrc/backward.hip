@@ -86,6 +86,7 @@ int check_backward(nslct_plan_t plan, int count, const void* G, const void* grad
         return fail(NSLCT_E_UNSUPPORTED, "backward runs complex64 or complex128 plans");
     if (!pair_size_ok(d.Nx) || !pair_size_ok(d.Ny))
         return fail(NSLCT_E_SIZE, "backward sides must be 8..1024 (2^k) or 48, 96, 192, 384, 768");
+    if (d.st.type == 7) return fail(NSLCT_E_UNSUPPORTED, "the backward sweep runs five-slot chains (not type 7)");
     if (grad_x == G) return fail(NSLCT_E_ARG, "grad_x must be distinct from G");
     return NSLCT_OK;
 }
@@ -175,6 +176,7 @@ int nslct_backward(nslct_plan_t plan, int count, const void* G, const void* grad
         return fail(NSLCT_E_UNSUPPORTED, "backward runs complex64 or complex128 plans");
     if (!pair_size_ok(d.Nx) || !pair_size_ok(d.Ny))
         return fail(NSLCT_E_SIZE, "backward sides must be 8..1024 (2^k) or 48, 96, 192, 384, 768");
+    if (d.st.type == 7) return fail(NSLCT_E_UNSUPPORTED, "the backward sweep runs five-slot chains (not type 7)");
     if (work == grad_x || work == G || work == grad_out || grad_x == G)
         return fail(NSLCT_E_ARG, "work and grad_x must be distinct from each other and from G");
     rc = ensure_device_ready();

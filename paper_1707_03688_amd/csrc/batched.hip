@@ -482,6 +482,10 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
             delete b;
             return fail(NSLCT_E_SIZE, "batched sides must be one of 64, 128, 192, 256, 384, 512, 768, 1024");
         }
+        if (d.st.type == 7) {
+            delete b;
+            return fail(NSLCT_E_UNSUPPORTED, "batches run five-slot chains (not the IDFT route, type 7)");
+        }
         b->plans[i].d = d;
         b->offsets[i] = (long long)b->total;
         b->total += (size_t)d.Nx * d.Ny;

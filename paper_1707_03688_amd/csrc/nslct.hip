@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(8 * fs_cols<T>()) nslct_col4096_step(PassArgs<
         // Register i now holds k1 = t + 8 i, i.e. FFT index k = j + 64 k1.
         const int lc = a.line_centered ? c - nl / 2 : (c >= (nl + 1) / 2 ? c - nl : c);
         const uint64_t l64 = (uint64_t)(int64_t)lc;
-        const uint64_t A0 = a.mid.c22 * (l64 * l64);
+        const uint64_t A0 = a.mid.c22 * (l64 * l64) + a.mid.c00;
         const uint64_t Bc = a.mid.c12 * l64;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(LinePlan<M>::TPL* LINES) nslct_bs_pass(PassArg
     const int lc = a.line_centered ? line - nl / 2 : (line >= (nl + 1) / 2 ? line - nl : line);
     const uint64_t l64 = (uint64_t)(int64_t)lc;
     auto chirp = [&](const ChirpArg& c, T scale) {
-        const uint64_t A = (COL ? c.c22 : c.c11) * (l64 * l64);
+        const uint64_t A = (COL ? c.c22 : c.c11) * (l64 * l64) + c.c00;
         const uint64_t Bc = c.c12 * l64;
         const uint64_t Q = COL ? c.c11 : c.c22;
 #pragma unroll

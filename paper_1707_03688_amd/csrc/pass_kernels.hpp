@@ -43,6 +43,7 @@ __global__ void init_twiddles_kernel() {
 
 struct ChirpArg {
     uint64_t c11, c12, c22;
+    uint64_t c00;  // constant phase (turns)
     int on;
 };
 
@@ -231,7 +232,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
     // sample).
     auto chirp = [&](const ChirpArg& c, T scale) {
         const uint64_t l64 = (uint64_t)(int64_t)lc;
-        const uint64_t A = (COL ? c.c22 : c.c11) * (l64 * l64);
+        const uint64_t A = (COL ? c.c22 : c.c11) * (l64 * l64) + c.c00;
         const uint64_t Bc = c.c12 * l64;
         const uint64_t Q = COL ? c.c11 : c.c22;
         const uint64_t t64 = (uint64_t)t;
@@ -428,7 +429,7 @@ constexpr int col_lines() {
 }
 
 
-ChirpArg to_arg(const ChirpTurns& c) { return {c.c11, c.c12, c.c22, c.nonzero}; }
+ChirpArg to_arg(const ChirpTurns& c) { return {c.c11, c.c12, c.c22, c.c00, c.nonzero}; }
 
 // Arguments of pass `pass` (0..4) of the five-slot chain whose chirps are
 // `turns[0..4]`, for an Nx x Ny image (host and device).

@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <functional>
 #include <thread>
@@ -512,6 +513,7 @@ ChirpTurns make_turns(const double p[3], double du, double dv) {
     c.c11 = turns_fixed(0.5L * (long double)p[0] * u * u);
     c.c12 = turns_fixed((long double)p[1] * u * v);
     c.c22 = turns_fixed(0.5L * (long double)p[2] * v * v);
+    c.c00 = 0;
     c.nonzero = (p[0] != 0.0 || p[1] != 0.0 || p[2] != 0.0) ? 1 : 0;
     return c;
 }
@@ -627,6 +629,50 @@ void fill_program(PlanData* p) {
                 g.p[2] = c;
             }
             g.npass = 3;
+        } else if (s.type == 7) {  // mats {P1', A, P3'}: j^q CM(P1') U^H CM_w(-A) U CM(P3') U^H
+            // Three line DFTs per axis (unnormalised): (Nx Ny)^(-3/2) in total.
+            const double sx = std::pow((double)p->Nx, -1.5), sy = std::pow((double)p->Ny, -1.5);
+            const uint64_t q = (uint64_t)(s.phase_q & 3);
+            if (d == 0) {
+                ProgPass a = prog_pass(0, 1, 0, 1, 1, +1, 0, 0);   // rows: IDFT_y
+                ProgPass b = prog_pass(1, 1, 0, 0, 2, +1, -1, 0);  // cols: IDFT_x CM(P3') DFT_x
+                b.mid = turns(s.mats[2], 1.0, false);
+                b.mid_on = 1;
+                ProgPass c = prog_pass(0, 0, 1, 0, 2, -1, +1, 0);  // rows: DFT_y CM_w(-A) IDFT_y
+                c.mid = turns(s.mats[1], -1.0, true);
+                c.mid_on = 1;
+                c.scale_mid = sy;
+                ProgPass e = prog_pass(1, 0, 1, 1, 1, +1, 0, 0);   // cols: IDFT_x CM(P1') j^q
+                e.mid = turns(s.mats[0], 1.0, false);
+                e.mid.c00 = q << 62;
+                e.mid.nonzero = e.mid.nonzero || q != 0;
+                e.mid_on = 1;
+                e.scale_mid = sx;
+                g.p[0] = a;
+                g.p[1] = b;
+                g.p[2] = c;
+                g.p[3] = e;
+            } else {  // adjoint: j^-q U CM(-P3') U^H CM_w(A) U CM(-P1')
+                ProgPass a = prog_pass(1, 1, 0, 1, 1, -1, 0, 0);   // cols: j^-q CM(-P1') DFT_x
+                a.pre = turns(s.mats[0], -1.0, false);
+                a.pre.c00 = ((4 - q) & 3) << 62;
+                a.pre_on = a.pre.nonzero || q != 0;
+                a.pre.nonzero = a.pre_on;
+                ProgPass b = prog_pass(0, 1, 0, 0, 2, -1, +1, 0);  // rows: DFT_y CM_w(A) IDFT_y
+                b.mid = turns(s.mats[1], 1.0, true);
+                b.mid_on = 1;
+                b.scale_mid = sy;
+                ProgPass c = prog_pass(1, 0, 1, 0, 2, +1, -1, 0);  // cols: IDFT_x CM(-P3') DFT_x
+                c.mid = turns(s.mats[2], -1.0, false);
+                c.mid_on = 1;
+                c.scale_mid = sx;
+                ProgPass e = prog_pass(0, 0, 1, 1, 1, -1, 0, 0);   // rows: DFT_y
+                g.p[0] = a;
+                g.p[1] = b;
+                g.p[2] = c;
+                g.p[3] = e;
+            }
+            g.npass = 4;
         }
     }
 }
@@ -652,6 +698,7 @@ void fill_chains(PlanData* p) {
         put(0, s.mats[2], 1.0);
         put(1, s.mats[1], -1.0);
         put(4, s.mats[0], 1.0);
+    } else if (s.type == 7) {  // no five-slot form (an IDFT is one of its factors)
     } else {  // CM(C)
         put(0, s.mats[0], 1.0);
     }
@@ -685,8 +732,8 @@ int check_common(int Nx, int Ny, double dx, double dy, const nslct_opts& o, std:
         *err = "split-precision sides must be 256 or 4096";
         return NSLCT_E_SIZE;
     }
-    if (o.type_override < 0 || o.type_override > 6) {
-        *err = "type_override must be in 0..6";
+    if (o.type_override < 0 || o.type_override > 7) {
+        *err = "type_override must be in 0..7";
         return NSLCT_E_ARG;
     }
     if (!(o.det_min > 0) || !std::isfinite(o.det_min)) {
@@ -701,6 +748,107 @@ int check_common(int Nx, int Ny, double dx, double dy, const nslct_opts& o, std:
 double gamma_ratio(const double x[3]) {
     return (std::fabs(x[0]) + std::fabs(x[1]) + 1.0) * (std::fabs(x[1]) + std::fabs(x[2]) + 1.0);
 }
+
+namespace {
+
+// ------------------------------------------- constant of the IDFT route
+// A Gaussian exp(-1/2 z^T S z) (S complex symmetric, Re S > 0) stays a
+// Gaussian under every factor of a chain; tracking its amplitude through two
+// factorisations of one matrix gives the ratio of their overall constants.
+//   CM(P):           S -> S - j P
+//   CC(B) (unitary): S -> (S^-1 + j B)^-1, amplitude / det(I + j S B)^(1/2),
+//                    the root continued from B = 0 along t B
+//   unitary IDFT:    S -> S^-1, amplitude / det(S)^(1/2), the root continued
+//                    from S = I along (1 - t) I + t S
+using cplxd = std::complex<double>;
+struct C2 {
+    cplxd a, b, c, d;  // [[a, b], [c, d]]
+};
+C2 c2_mul(const C2& x, const C2& y) {
+    return {x.a * y.a + x.b * y.c, x.a * y.b + x.b * y.d, x.c * y.a + x.d * y.c, x.c * y.b + x.d * y.d};
+}
+cplxd c2_det(const C2& x) { return x.a * x.d - x.b * x.c; }
+C2 c2_inv(const C2& x) {
+    const cplxd r = 1.0 / c2_det(x);
+    return {x.d * r, -x.b * r, -x.c * r, x.a * r};
+}
+C2 c2_real(const double m[3]) { return {m[0], m[1], m[1], m[2]}; }
+
+template <class Fn>
+cplxd root_continued(Fn at) {
+    cplxd prev = 1.0;
+    const int steps = 512;
+    for (int k = 1; k <= steps; ++k) {
+        cplxd r = std::sqrt(c2_det(at((double)k / steps)));
+        if (std::abs(r - prev) > std::abs(r + prev)) r = -r;
+        prev = r;
+    }
+    return prev;
+}
+
+struct Factor {
+    int kind;  // 0 CM, 1 unitary CC, 2 unitary IDFT
+    const double* m;
+};
+
+cplxd track_amplitude(const Factor* f, int n, C2* S) {
+    cplxd amp = 1.0;
+    const cplxd j(0.0, 1.0);
+    for (int i = 0; i < n; ++i) {
+        if (f[i].kind == 0) {
+            const C2 P = c2_real(f[i].m);
+            *S = {S->a - j * P.a, S->b - j * P.b, S->c - j * P.c, S->d - j * P.d};
+        } else if (f[i].kind == 1) {
+            const C2 B = c2_real(f[i].m);
+            const C2 S0 = *S;
+            const C2 SB = c2_mul(S0, B);
+            amp /= root_continued([&](double t) {
+                return C2{1.0 + j * t * SB.a, j * t * SB.b, j * t * SB.c, 1.0 + j * t * SB.d};
+            });
+            const C2 Si = c2_inv(S0);
+            *S = c2_inv({Si.a + j * B.a, Si.b + j * B.b, Si.c + j * B.c, Si.d + j * B.d});
+        } else {
+            const C2 S0 = *S;
+            amp /= root_continued([&](double t) {
+                return C2{(1.0 - t) + t * S0.a, t * S0.b, t * S0.c, (1.0 - t) + t * S0.d};
+            });
+            *S = c2_inv(S0);
+        }
+    }
+    return amp;
+}
+
+// j^q with the route (type 7) equal to the HA chain `ha` of the same matrix;
+// -1 if the ratio of the amplitudes is not a power of j (not the same matrix).
+int route_phase(const nslct_stages& ha, const double mats[4][3]) {
+    const C2 S0{1.1, -0.2, -0.2, 0.9};
+    Factor fh[4];
+    if (ha.type == 1) {  // CC(H), CM(P3), CC(B'), CM(P1) in application order
+        fh[0] = {1, ha.mats[3]};
+        fh[1] = {0, ha.mats[2]};
+        fh[2] = {1, ha.mats[1]};
+        fh[3] = {0, ha.mats[0]};
+    } else {  // CM(Q3), CC(B1'), CM(Q1), CC(H1)
+        fh[0] = {0, ha.mats[3]};
+        fh[1] = {1, ha.mats[2]};
+        fh[2] = {0, ha.mats[1]};
+        fh[3] = {1, ha.mats[0]};
+    }
+    const Factor fr[4] = {{2, nullptr}, {0, mats[2]}, {1, mats[1]}, {0, mats[0]}};
+    C2 Sh = S0, Sr = S0;
+    const cplxd ah = track_amplitude(fh, 4, &Sh);
+    const cplxd ar = track_amplitude(fr, 4, &Sr);
+    const double smax = std::max({std::abs(Sh.a), std::abs(Sh.b), std::abs(Sh.d), 1.0});
+    if (std::max({std::abs(Sh.a - Sr.a), std::abs(Sh.b - Sr.b), std::abs(Sh.d - Sr.d)}) > 1e-8 * smax) return -1;
+    const cplxd k = ah / ar;
+    const int q = ((int)std::lround(std::arg(k) / (0.25 * kTwoPi)) % 4 + 4) % 4;
+    const cplxd jq = q == 0 ? cplxd(1, 0) : q == 1 ? cplxd(0, 1) : q == 2 ? cplxd(-1, 0) : cplxd(0, -1);
+    return std::abs(k - jq) <= 1e-6 ? q : -1;
+}
+
+bool route_spacing_ok(int N, double d) { return std::fabs(d * d * N / kTwoPi - 1.0) <= 1e-12; }
+
+}  // namespace
 
 namespace {
 int build_plan_from(const double abcd[16], int Nx, int Ny, double dx, double dy, const nslct_opts& o,
@@ -818,7 +966,7 @@ int build_plan_from(const double abcd[16], int Nx, int Ny, double dx, double dy,
         fill_chains(out);
         return NSLCT_OK;
     }
-    if (o.type_override >= 4) {  // LC-NsDLCT: rank-one gauge (eqs. LC04-LC10)
+    if (o.type_override >= 4 && o.type_override <= 6) {  // LC-NsDLCT: rank-one gauge (eqs. LC04-LC10)
         Gauge g{b, 1, dmin};
         double best = INFINITY, bh[3] = {0, 0, 0};
         int btype = 0;
@@ -851,10 +999,63 @@ int build_plan_from(const double abcd[16], int Nx, int Ny, double dx, double dy,
             *err = "no rank-one gauge with invertible B' (eqs. LC08, LC10)";
             return NSLCT_E_NO_DECOMPOSITION;
         }
-        // Neither rank-one form gives an invertible B': the HA-NsDLCT is used
-        // instead (Sec. 4.2.2), its type by the trace rule.
+        // Neither rank-one form gives an invertible B' (Sec. 4.2.2): for
+        // a12 = a21 = 0 the IDFT route where it applies, else the HA-NsDLCT,
+        // its type by the trace rule.
     }
-    int type = o.type_override >= 4 ? 0 : o.type_override;
+    if (o.type_override == 7 || o.type_override == 6) {
+        const double amax = std::max({std::fabs(b.A.a11), std::fabs(b.A.a12), std::fabs(b.A.a21), std::fabs(b.A.a22)});
+        const double sc = std::max(1.0, mmax);
+        std::string why;
+        int wrc = NSLCT_OK;
+        if (std::fabs(b.A.a12) > 1e-12 * sc || std::fabs(b.A.a21) > 1e-12 * sc) {
+            why = "the IDFT route needs a12 = a21 = 0 (Sec. 4.2.2)";
+            wrc = NSLCT_E_NO_DECOMPOSITION;
+        } else if (!(std::fabs(det(b.A)) >= o.det_min * std::max(1.0, amax * amax))) {
+            why = "the IDFT route needs an invertible A (eq. Bsym08 for (-B, A; -D, C))";
+            wrc = NSLCT_E_NO_DECOMPOSITION;
+        } else if (!route_spacing_ok(Nx, dx) || !route_spacing_ok(Ny, dy)) {
+            why = "the IDFT route keeps the grid only at dx = sqrt(2 pi / Nx), dy = sqrt(2 pi / Ny)";
+            wrc = NSLCT_E_UNSUPPORTED;
+        } else if (!native_size(Nx) || !native_size(Ny)) {
+            why = "the IDFT route runs native lengths (2^k, 3 * 2^k) only";
+            wrc = NSLCT_E_SIZE;
+        } else if (o.precision != NSLCT_C64 && o.precision != NSLCT_C128) {
+            why = "the IDFT route runs complex64 / complex128 only";
+            wrc = NSLCT_E_UNSUPPORTED;
+        }
+        if (wrc == NSLCT_OK) {
+            // The HA chain of M fixes the operator the route must equal.
+            nslct_opts oh = o;
+            oh.type_override = 0;
+            PlanData ha;
+            const int hrc = build_plan_from(abcd, Nx, Ny, dx, dy, oh, &ha, err, nullptr, false);
+            if (hrc) return hrc;
+            const double dt = det(b.A);
+            const M2 Ai{b.A.a22 / dt, -b.A.a12 / dt, -b.A.a21 / dt, b.A.a11 / dt};
+            const M2 mB{-b.B.a11, -b.B.a12, -b.B.a21, -b.B.a22};
+            double mats[4][3] = {};
+            sym3(mul(minus_eye(b.C), Ai), mats[0]);  // P1' = (C - I) A^-1
+            sym3(b.A, mats[1]);
+            sym3(mul(Ai, minus_eye(mB)), mats[2]);   // P3' = A^-1 (-B - I)
+            const int q = route_phase(ha.st, mats);
+            if (q < 0) {
+                *err = "IDFT route: the two factorisations do not reach the same matrix";
+                return NSLCT_E_NO_DECOMPOSITION;
+            }
+            s.type = 7;
+            s.phase_q = q;
+            std::memcpy(s.mats, mats, sizeof mats);
+            s.gauge_objective = gamma_ratio(mats[0]) * gamma_ratio(mats[1]) * gamma_ratio(mats[2]);
+            fill_chains(out);
+            return NSLCT_OK;
+        }
+        if (o.type_override == 7) {
+            *err = why;
+            return wrc;
+        }
+    }
+    int type = o.type_override >= 4 ? 0 : o.type_override;  // 6 (and 7 handled above): trace rule
     if (type == 0) type = (b.B.a11 + b.B.a22) < 0 ? 2 : 1;
     Gauge g{b, type, dmin};
     GaugeOut go;
@@ -883,11 +1084,25 @@ int build_plan_from_stages(const nslct_stages& st, int Nx, int Ny, const nslct_o
                            std::string* err) {
     int rc = check_common(Nx, Ny, st.dx, st.dy, o, err);
     if (rc) return rc;
-    if (st.type < 0 || st.type > 5) {
-        *err = "stage type must be in 0..5";
+    if (st.type < 0 || st.type > 7 || st.type == 6) {
+        *err = "stage type must be in 0..5 or 7";
         return NSLCT_E_ARG;
     }
-    const int nm = st.type == 0 ? 1 : st.type == 3 ? 3 : 4;
+    if (st.type == 7) {
+        if (!route_spacing_ok(Nx, st.dx) || !route_spacing_ok(Ny, st.dy)) {
+            *err = "the IDFT route keeps the grid only at dx = sqrt(2 pi / Nx), dy = sqrt(2 pi / Ny)";
+            return NSLCT_E_UNSUPPORTED;
+        }
+        if (!native_size(Nx) || !native_size(Ny)) {
+            *err = "the IDFT route runs native lengths (2^k, 3 * 2^k) only";
+            return NSLCT_E_SIZE;
+        }
+        if (o.precision != NSLCT_C64 && o.precision != NSLCT_C128) {
+            *err = "the IDFT route runs complex64 / complex128 only";
+            return NSLCT_E_UNSUPPORTED;
+        }
+    }
+    const int nm = st.type == 0 ? 1 : (st.type == 3 || st.type == 7) ? 3 : 4;
     if ((st.type == 4 && (st.mats[3][1] != 0 || st.mats[3][2] != 0)) ||
         (st.type == 5 && (st.mats[3][0] != 0 || st.mats[3][1] != 0))) {
         *err = "LC stages need H = (h, 0; 0, 0) (type 4) or (0, 0; 0, h) (type 5)";
@@ -907,8 +1122,9 @@ int build_plan_from_stages(const nslct_stages& st, int Nx, int Ny, const nslct_o
     s.type = st.type;
     for (int i = 0; i < nm; ++i)
         for (int k = 0; k < 3; ++k) s.mats[i][k] = st.mats[i][k];
-    if (st.type >= 4)
+    if (st.type == 4 || st.type == 5)
         for (int k = 0; k < 3; ++k) s.h[k] = st.mats[3][k];
+    if (st.type == 7) s.phase_q = st.phase_q & 3;
     s.dx = st.dx;
     s.dy = st.dy;
     s.dwx = kTwoPi / (Nx * st.dx);
@@ -1199,6 +1415,10 @@ int plan_jacobian(const double abcd[16], const double theta0[10], int Nx, int Ny
 int plan_theta_jacobian(const PlanData& p, double jac[12 * 10], std::string* err) {
     if (!p.has_lie) {
         *err = "the plan was made from stage matrices: no ABCD parameterisation to differentiate";
+        return NSLCT_E_UNSUPPORTED;
+    }
+    if (p.st.type == 7) {
+        *err = "the IDFT route (type 7) has no decomposition of the same type at perturbed matrices";
         return NSLCT_E_UNSUPPORTED;
     }
     if (p.st.type == 3 && p.opts.type_override == 0) {

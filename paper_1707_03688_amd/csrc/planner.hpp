@@ -15,6 +15,7 @@ namespace nslct {
 // modulo 2*pi and a product with exact integer sample indices is exact.
 struct ChirpTurns {
     uint64_t c11, c12, c22;
+    uint64_t c00;  // constant phase (turns), added once per line
     int nonzero;
 };
 

@@ -63,7 +63,7 @@ __global__ void __launch_bounds__((split_lines<N, COL>() * N / 16)) nslct_split_
             const int e = p >= (N + 1) / 2 ? p - N : p;
             const uint64_t l64 = (uint64_t)(int64_t)lc, e64 = (uint64_t)(int64_t)e;
             const uint64_t ph = (COL ? c.c22 : c.c11) * (l64 * l64) + c.c12 * (l64 * e64) +
-                                (COL ? c.c11 : c.c22) * (e64 * e64);
+                                (COL ? c.c11 : c.c22) * (e64 * e64) + c.c00;
             cplx<float>& v = lds[ln * LL + lds_pad(p)];
             v = cmul(v, turns_cs(ph, scale));
         }

@@ -66,7 +66,7 @@ def test_error_codes(nl):
     affine = np.block([[2 * np.eye(2), np.zeros((2, 2))], [np.zeros((2, 2)), 0.5 * np.eye(2)]])
     assert _cplan(nl, affine) == -3                    # B = 0, A != I
     o = nl.lib.opts()
-    o.type_override = 7
+    o.type_override = 8
     assert _cplan(nl, M, opts=o) == -1
     # Null pointers and misaligned buffers are rejected before any device work.
     p = nl.Plan(M, 16, 16)
@@ -409,3 +409,44 @@ def test_reduced_types_at_bluestein_lengths_use_five_passes(nl):
     M = next(synth.symplectic_candidates(11))
     p = nl.Plan(M, 100, 100, 0.25, 0.25, type_override=6)
     assert p.stages()["type"] in (4, 5) and p.passes() == 5
+
+
+def test_route_plans_match_the_oracle(nl):
+    """Type 7, the (-B, A; -D, C)(0, -I; I, 0) route of Sec. 4.2.2 for
+    a12 = a21 = 0: the planner's stages and constant j^phase_q equal the
+    oracle's (whose paper-constant IDFT and CC contribute a factor -j * -1 =
+    j: j^q = j kappa); type_override 6 takes the route when no rank-one gauge
+    exists; the route is refused off its spacing, for a12 != 0, by the
+    theta-Jacobian and by the ragged batch; from-stages plans round-trip."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import route
+    from test_oracle_route import route_matrices
+    qs = set()
+    for N, Ny in ((64, 64), (128, 32)):
+        dx, dy = math.sqrt(2 * math.pi / N), math.sqrt(2 * math.pi / Ny)
+        for M in route_matrices(6, 6):
+            p = nl.Plan(M, N, Ny, dx, dy, type_override=7)
+            st = p.stages()
+            pr = route.route_plan(M, N, Ny, dx, dy, oplan.plan(M, N, Ny, dx, dy))
+            assert st["type"] == 7 and p.passes() == 4
+            for a, b in zip(st["mats"][:3], pr.mats):
+                assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.max(np.abs(b)))
+            assert abs(1j ** st["phase_q"] - 1j * pr.kappa) <= 1e-9
+            qs.add(st["phase_q"])
+            assert nl.Plan(M, N, Ny, dx, dy, type_override=6).stages()["type"] == 7
+            q = nl.Plan.from_stages(7, st["mats"][:3], N, Ny, dx, dy, phase_q=st["phase_q"]).stages()
+            assert q["type"] == 7 and q["phase_q"] == st["phase_q"]
+            with pytest.raises(nl.NslctError) as e:
+                p.theta_jacobian()
+            assert e.value.code == -6
+    assert qs == {1, 3}
+    M = route_matrices(6, 1)[0]
+    d = math.sqrt(2 * math.pi / 64)
+    assert _cplan(nl, M, 64, 64, 1.1 * d, d, opts=_opts(nl, 7)) == -6
+    assert nl.Plan(M, 64, 64, 1.1 * d, d, type_override=6).stages()["type"] in (1, 2)
+    assert _cplan(nl, next(synth.symplectic_candidates(7)), 64, 64, d, d, opts=_opts(nl, 7)) == -3
+    p7 = nl.Plan(M, 64, 64, d, d, type_override=7)
+    arr = (ctypes.c_void_p * 1)(p7._h.value)
+    h = ctypes.c_void_p()
+    assert nl.lib.nslct_batch_create(arr, 1, ctypes.byref(h)) == -6

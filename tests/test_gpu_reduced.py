@@ -179,3 +179,45 @@ def test_reduced_chains_at_bluestein_lengths(torch, nl, typ, precision):
     tol = 1e-5 if precision == "c64" else 1e-11
     assert chain.rel_l2(p.forward(x).cpu().numpy(), fast.forward(po, g)) <= tol
     assert chain.rel_l2(p.inverse(x).cpu().numpy(), fast.inverse(po, g)) <= tol
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+@pytest.mark.parametrize("shape", [(64, 64), (128, 32), (48, 96)])
+def test_idft_route_matches_oracle_and_the_ha_chain(torch, nl, shape, precision):
+    """Type 7 (Sec. 4.2.2, a12 = a21 = 0: IDFT then CM-CC-CM of
+    (-B, A; -D, C)), four passes: forward and inverse against the oracle's
+    route; on a smooth input the same operator as the HA chain of the matrix
+    (the derived constant), not its negative (a sign test: the two discretisations of
+    one operator agree to a few 1e-2 on grids as small as 32 samples, the
+    negated one is 2 away); the pass-by-pass launch equals the forward transform
+    bitwise."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import plan as oplan, route
+    from test_oracle_route import route_matrices
+    Nx, Ny = shape
+    dx, dy = math.sqrt(2 * math.pi / Nx), math.sqrt(2 * math.pi / Ny)
+    dt = torch.complex64 if precision == "c64" else torch.complex128
+    tol = 1e-5 if precision == "c64" else 1e-11
+    x_ = (np.arange(Nx) - Nx // 2) * dx
+    y_ = (np.arange(Ny) - Ny // 2) * dy
+    X, Y = np.meshgrid(x_, y_, indexing="ij")
+    smooth = np.exp(-0.6 * X * X - 0.4 * Y * Y + 0.2j * X * Y + 0.3j * X)
+    for M in route_matrices(Nx + Ny, 3):
+        p = nl.Plan(M, Nx, Ny, dx, dy, precision=precision, type_override=7)
+        assert p.passes() == 4
+        pr = route.route_plan(M, Nx, Ny, dx, dy, oplan.plan(M, Nx, Ny, dx, dy))
+        g = synth.complex_normal(shape, seed=Nx * Ny + 1)
+        x = torch.from_numpy(g).to(dt).cuda()
+        G = p.forward(x)
+        assert chain.rel_l2(G.cpu().numpy(), route.forward(pr, g)) <= tol
+        assert chain.rel_l2(p.inverse(x).cpu().numpy(), route.inverse(pr, g)) <= tol
+        z = torch.empty_like(x)
+        for k in range(4):
+            p.launch_pass(0, k, x if k == 0 else z, z)
+        assert torch.equal(z, G)
+        ph = nl.Plan(M, Nx, Ny, dx, dy, precision=precision)  # HA chain of M
+        s = torch.from_numpy(smooth).to(dt).cuda()
+        a, b = p.forward(s).cpu().numpy(), ph.forward(s).cpu().numpy()
+        assert chain.rel_l2(a, b) <= 5e-2 and chain.rel_l2(a, -b) >= 1.9
