@@ -169,6 +169,28 @@ def test_many_inplace_and_passes_are_bitwise_consistent(torch, nl):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("shape,count,precision", [((1024, 1024), 8, "c64"), ((512, 512), 32, "c64"),
+                                                    ((256, 384), 24, "c128")])
+def test_multi_image_launches_are_bitwise(torch, nl, shape, count, precision):
+    """Multi-image launches at full size (thousands of workgroups per pass)
+    give the bits of one-image launches, forward and inverse, in place too."""
+    M = _draws(29, 1)[0]
+    Nx, Ny = shape
+    d = math.sqrt(2 * math.pi / max(Nx, Ny))
+    pg = nl.Plan(M, Nx, Ny, d, d, precision=precision)
+    x = _to_gpu(torch, synth.complex_normal((count, Nx, Ny), seed=7), precision)
+    many = pg.forward(x)
+    for b in (0, count // 2, count - 1):
+        assert torch.equal(pg.forward(x[b].contiguous()), many[b])
+    y = x.clone()
+    pg.forward(y, out=y)
+    assert torch.equal(y, many)
+    back = pg.inverse(many)
+    for b in (0, count - 1):
+        assert torch.equal(pg.inverse(many[b].contiguous()), back[b])
+    torch.cuda.synchronize()
+
+
 def test_planner_plan_runs_and_matches_oracle_at_its_stages(torch, nl):
     """nslct_plan (C++ gauge search) end to end; parity at the planner's stages."""
     for M in _draws(24, 3) + [symplectic.project(paper_matrices()["M1"])]:

@@ -221,3 +221,39 @@ def test_idft_route_matches_oracle_and_the_ha_chain(torch, nl, shape, precision)
         s = torch.from_numpy(smooth).to(dt).cuda()
         a, b = p.forward(s).cpu().numpy(), ph.forward(s).cpu().numpy()
         assert chain.rel_l2(a, b) <= 5e-2 and chain.rel_l2(a, -b) >= 1.9
+
+
+@pytest.mark.parametrize("shape", [(512, 12), (1024, 48), (2048, 8)])
+def test_out_of_place_in_place_and_pass_launches_agree(torch, nl, shape):
+    """Complex64 chains with 512-, 1024- and 2048-long columns (4-column
+    tiles): out-of-place, in-place and pass-by-pass execution give the same
+    bits for the HA chain and every reduced schedule (types 3, 4, 5, 7),
+    forward and inverse; the HA chain matches the oracle."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import plan as oplan
+    from test_oracle_route import route_matrices
+    Nx, Ny = shape
+    dx, dy = math.sqrt(2 * math.pi / Nx), math.sqrt(2 * math.pi / Ny)
+    g = synth.complex_normal((2, Nx, Ny), seed=Nx + Ny)
+    x = torch.from_numpy(g).to(torch.complex64).cuda()
+    M_ha = next(synth.symplectic_candidates(Nx))
+    cases = [(M_ha, 0), (_cmccm_matrix(5), 3), (_lc_matrix(6), 4), (_lc_matrix(7), 5),
+             (next(iter(route_matrices(Nx + Ny, 1))), 7)]
+    for M, typ in cases:
+        p = nl.Plan(M, Nx, Ny, dx, dy, type_override=typ)
+        for direction, run in ((0, p.forward), (1, p.inverse)):
+            out = run(x)
+            y = x.clone()
+            run(y, out=y)
+            assert torch.equal(out, y), (typ, direction)
+            z = torch.empty_like(x)
+            for k in range(p.passes()):
+                p.launch_pass(direction, k, x if k == 0 else z, z)
+            assert torch.equal(out, z), (typ, direction)
+        if typ == 0:
+            st = p.stages()
+            po = oplan.plan_from_stages(st["type"], st["mats"], Nx, Ny, dx, dy)
+            assert chain.rel_l2(p.forward(x[0]).cpu().numpy(), chain.forward(po, g[0])) <= 1e-5
+    torch.cuda.synchronize()
