@@ -316,16 +316,27 @@ GaugeOut solve(const Gauge& g, double mmax, const double* start = nullptr) {
         step = 1e-3 * (1.0 + std::fabs(s0[0]) + std::fabs(s0[1]) + std::fabs(s0[2]));
     }
     // Grid evaluation.
-    std::vector<std::pair<double, std::array<int, 3>>> cells;
-    if (!start) cells.reserve(dim == 2 ? G * G : G * G * G);
+    using Cell = std::pair<double, std::array<int, 3>>;
+    // Cells ordered by objective, ties by cell index: a strict total order,
+    // so the selections below do not depend on how the grid was split.
+    auto less = [](const Cell& x, const Cell& y) {
+        return x.first < y.first || (x.first == y.first && x.second < y.second);
+    };
+    constexpr size_t kHead = 4096;
+    std::vector<std::vector<Cell>> part;
+    std::vector<Cell> cells;  // the best cells, in order
     if (!start) {
-        // The grid's rows are evaluated by up to 16 host threads; the cells
-        // are gathered in row order (the same list as a serial sweep).
+        // The grid's rows are swept by up to 16 host threads, each into a
+        // vector of its own (moved into `part` at the end, so no two threads
+        // write to neighbouring memory), which it also partially orders: its
+        // best kHead cells first.  The best kHead cells of the grid are among
+        // the union of those heads.
         const int G3 = dim == 3 ? G : 1;
         const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        std::vector<std::vector<std::pair<double, std::array<int, 3>>>> part(nth);
-        for (auto& pv : part) pv.reserve((size_t)(G / nth + 1) * G * G3);
+        part.resize(nth);
         auto rows = [&](int t) {
+            std::vector<Cell> local;
+            local.reserve((size_t)(G / nth + 1) * G * G3);
             double s[3] = {0, 0, 0};
             for (int i = t; i < G; i += nth)
                 for (int j = 0; j < G; ++j)
@@ -334,31 +345,24 @@ GaugeOut solve(const Gauge& g, double mmax, const double* start = nullptr) {
                         s[1] = -R + step * j;
                         s[2] = -R + step * k;
                         const double f = fs(s);
-                        if (std::isfinite(f)) part[t].push_back({f, {i, j, k}});
+                        if (std::isfinite(f)) local.push_back({f, {i, j, k}});
                     }
+            if (local.size() > kHead) std::nth_element(local.begin(), local.begin() + (kHead - 1), local.end(), less);
+            part[t] = std::move(local);
         };
         std::vector<std::thread> pool;
         for (int t = 1; t < nth; ++t) pool.emplace_back(rows, t);
         rows(0);
         for (auto& th : pool) th.join();
-        std::vector<size_t> at(nth, 0);
-        for (int i = 0; i < G; ++i) {  // row i was swept by thread i mod nth
-            auto& pv = part[i % nth];
-            size_t& a = at[i % nth];
-            while (a < pv.size() && pv[a].second[0] == i) cells.push_back(pv[a++]);
-        }
+        for (const auto& pv : part) cells.insert(cells.end(), pv.begin(), pv.begin() + std::min(pv.size(), kHead));
     }
     if (!start) {
         if (cells.empty()) return out;
         // Seeds: the best cells in increasing objective, each more than three
         // cells away from the seeds already taken, at most 16.  Only the head
-        // of the order is needed: the best `head` cells are selected and
-        // sorted, and the full order is taken only if they hold fewer than 16
-        // seeds (same seeds either way; ties ordered by cell index).
-        auto less = [](const std::pair<double, std::array<int, 3>>& x,
-                       const std::pair<double, std::array<int, 3>>& y) {
-            return x.first < y.first || (x.first == y.first && x.second < y.second);
-        };
+        // of the order is needed: the best kHead cells are sorted, and the
+        // whole grid is sorted only if they hold fewer than 16 seeds (same
+        // seeds either way).
         auto pick = [&](size_t n, std::vector<std::array<int, 3>>& seeds) {
             seeds.clear();
             for (size_t c = 0; c < n; ++c) {
@@ -374,11 +378,16 @@ GaugeOut solve(const Gauge& g, double mmax, const double* start = nullptr) {
             }
             return false;
         };
+        size_t total = 0;
+        for (const auto& pv : part) total += pv.size();
         std::vector<std::array<int, 3>> seeds;
-        const size_t head = std::min<size_t>(cells.size(), 4096);
+        const size_t head = std::min(cells.size(), kHead);
         std::nth_element(cells.begin(), cells.begin() + (head - 1), cells.end(), less);
         std::sort(cells.begin(), cells.begin() + head, less);
-        if (!pick(head, seeds) && head < cells.size()) {
+        if (!pick(head, seeds) && head < total) {
+            cells.clear();
+            cells.reserve(total);
+            for (const auto& pv : part) cells.insert(cells.end(), pv.begin(), pv.end());
             std::sort(cells.begin(), cells.end(), less);
             pick(cells.size(), seeds);
         }
