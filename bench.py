@@ -210,6 +210,7 @@ def bench_batched(nl, torch, synth, np, count=256, seed=2):
             "pct_hbm_peak": 80.0 * px / t_graph / 1e9 / HBM_PEAK_GBPS * 100,
             "schedule": {f"{'cols' if c else 'rows'} {N}": f"{v['lines']} lines x "
                          + (f"{v['mult']}/CU" if v["mult"] else "1 WG/item")
+                         + (", alternative line plan" if v["plan"] else "")
                          for (c, N), v in b.schedules().items()}}
 
 

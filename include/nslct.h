@@ -204,12 +204,14 @@ int nslct_plan_passes(nslct_plan_t plan, int* npasses);
  * batch copies the plans (they may be destroyed afterwards), uploads a
  * table of pass arguments per (image, direction, pass) and an XCD-balanced
  * work list to the current device.  Its passes run one launch per group
- * (pass axis, line length); each group's schedule, the tile width (lines
- * per work item: 256, 512 or 1024 threads' worth, as LDS allows) and the
- * grid (1, 2, 4 or 8 persistent workgroups per CU, or one workgroup per
- * item), is taken from the schedule cache or chosen by timing every
- * candidate on scratch images (device work and allocation happen here,
- * once).  The schedule cache is a text file keyed by (GPU architecture,
+ * (pass axis, line length); each group's schedule, the line plan (0: the
+ * single-image split of a line over threads and radices; 1: an
+ * alternative split, e.g. 1024 = 16 x 4 x 16 on 32 instead of 64 threads),
+ * the tile width (lines per work item: 256, 512 or 1024 threads' worth, as
+ * LDS allows) and the grid (1, 2, 4 or 8 persistent workgroups per CU, or
+ * one workgroup per item), is taken from the schedule cache or chosen by
+ * timing every candidate on scratch images (device work and allocation
+ * happen here, once).  The schedule cache is a text file keyed by (GPU architecture,
  * precision, axis, line length, lines of the group rounded up to a power of
  * two): NSLCT_TUNE_CACHE names it (off: no cache), default
  * $HOME/.cache/nslct/batch_schedule.txt; unwritable paths only disable it.
@@ -225,15 +227,18 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
 int nslct_batch_info(nslct_batch_t batch, size_t* total_samples, int* mult, double* tuned_us);
 
 /* Schedule of the group of pass axis `col` (0: row passes, lines of length
- * Ny; 1: column passes, lines of length Nx) and line length N: lines per
- * work item, grid (workgroups per CU, 0 = one per item) and whether it came
- * from the schedule cache.  NSLCT_E_ARG when the batch has no such group. */
-int nslct_batch_group(nslct_batch_t batch, int col, int N, int* lines, int* mult, int* cached);
+ * Ny; 1: column passes, lines of length Nx) and line length N: line plan,
+ * lines per work item, grid (workgroups per CU, 0 = one per item) and
+ * whether it came from the schedule cache (any output pointer may be NULL).
+ * NSLCT_E_ARG when the batch has no such group. */
+int nslct_batch_group(nslct_batch_t batch, int col, int N, int* plan, int* lines, int* mult, int* cached);
 
-/* Sets one group's tile width (`lines`, one of its candidates) and grid
- * (mult as nslct_batch_set_grid); synchronises the batch's device and drops
- * the captured graphs.  Results do not depend on the schedule. */
-int nslct_batch_set_group(nslct_batch_t batch, int col, int N, int lines, int mult);
+/* Sets one group's line plan (0 or 1), tile width (`lines`, a candidate of
+ * that plan) and grid (mult as nslct_batch_set_grid); synchronises the
+ * batch's device and drops the captured graphs.  Results agree across
+ * schedules to rounding (bitwise across tile widths and grids of one line
+ * plan; the two line plans order their additions differently). */
+int nslct_batch_set_group(nslct_batch_t batch, int col, int N, int plan, int lines, int mult);
 
 /* Puts every group on `mult` persistent workgroups per CU (1, 2, 4 or 8) or
  * on one workgroup per work item (0), keeping the tile widths; any other

@@ -261,11 +261,12 @@ class Batch:
         self.mult = int(mult)
 
     def group(self, col: int, N: int) -> dict:
-        """Schedule of one group (``nslct_batch_group``)."""
-        lines, mult, cached = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        check(lib.nslct_batch_group(self._h, int(col), int(N), ctypes.byref(lines), ctypes.byref(mult),
-                                    ctypes.byref(cached)))
-        return {"lines": lines.value, "mult": mult.value, "cached": bool(cached.value)}
+        """Schedule of one group (``nslct_batch_group``): line plan, lines per
+        work item, grid (workgroups per CU, 0 = one per item), cached."""
+        plan, lines, mult, cached = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib.nslct_batch_group(self._h, int(col), int(N), ctypes.byref(plan), ctypes.byref(lines),
+                                    ctypes.byref(mult), ctypes.byref(cached)))
+        return {"plan": plan.value, "lines": lines.value, "mult": mult.value, "cached": bool(cached.value)}
 
     def schedules(self) -> dict:
         """Schedules of every group: {(col, N): {...}}."""
@@ -275,9 +276,9 @@ class Batch:
                 out[(col, N)] = self.group(col, N)
         return out
 
-    def set_group(self, col: int, N: int, lines: int, mult: int):
-        """Set one group's tile width and grid (``nslct_batch_set_group``)."""
-        check(lib.nslct_batch_set_group(self._h, int(col), int(N), int(lines), int(mult)))
+    def set_group(self, col: int, N: int, lines: int, mult: int, plan: int = 0):
+        """Set one group's line plan, tile width and grid (``nslct_batch_set_group``)."""
+        check(lib.nslct_batch_set_group(self._h, int(col), int(N), int(plan), int(lines), int(mult)))
 
     def views(self, flat):
         """Per-image [Nx, Ny] views of a packed tensor."""

@@ -72,8 +72,8 @@ SIGNATURES = {
     "nslct_batch_create": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P)]),
     "nslct_batch_info": (I, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(I), ctypes.POINTER(D)]),
     "nslct_batch_set_grid": (I, [P, I]),
-    "nslct_batch_group": (I, [P, I, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
-    "nslct_batch_set_group": (I, [P, I, I, I, I]),
+    "nslct_batch_group": (I, [P, I, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+    "nslct_batch_set_group": (I, [P, I, I, I, I, I]),
     "nslct_forward_batched": (I, [P, P, P, P]),
     "nslct_inverse_batched": (I, [P, P, P, P]),
     "nslct_batch_run": (I, [P, I, I, P, P, P]),

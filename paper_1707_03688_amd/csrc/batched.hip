@@ -12,6 +12,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -50,16 +51,19 @@ struct BatchArgs {
 #define NSLCT_BATCH_SIZES(X) X(64) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
 // Tile widths of a work item: W = 0, 1, 2 give 256, 512, 1024 threads, i.e.
-// (256 << W) / TPL lines (row passes W <= 1).  A width is a candidate when
-// its lines fit the 160 KB of LDS.
+// (256 << W) / TPL lines (row passes W <= 1), for line plan V (PlanVariant:
+// 0 the single-image plan, 1 the alternative).  A (width, plan) pair is a
+// candidate when the plan exists and its lines fit the 160 KB of LDS.
 constexpr int kMaxWidth = 2;
-template <int N, int W>
+constexpr int kPlans = 2;
+template <int N, int W, int V>
 constexpr int width_lines() {
-    return (256 << W) / LinePlan<N>::TPL;
+    return (256 << W) / PlanVariant<N, V>::TPL;
 }
-template <typename T, int N, bool COL, int W>
+template <typename T, int N, bool COL, int W, int V>
 constexpr bool width_ok() {
-    return (COL || W <= 1) && width_lines<N, W>() * lds_line_elems<N>() * (int)sizeof(cplx<T>) <= 160 * 1024;
+    return PlanVariant<N, V>::exists && (COL || W <= 1) &&
+           width_lines<N, W, V>() * lds_line_elems<N>() * (int)sizeof(cplx<T>) <= 160 * 1024;
 }
 
 bool batch_size_ok(int n) {
@@ -73,34 +77,42 @@ bool batch_size_ok(int n) {
     }
 }
 
-template <int N>
-bool host_width_ok_n(int w, bool col, bool dbl) {
+template <int N, int V>
+bool host_width_ok_v(int w, bool col, bool dbl) {
     switch (w) {
-        case 0: return dbl ? (col ? width_ok<double, N, true, 0>() : width_ok<double, N, false, 0>())
-                           : (col ? width_ok<float, N, true, 0>() : width_ok<float, N, false, 0>());
-        case 1: return dbl ? (col ? width_ok<double, N, true, 1>() : width_ok<double, N, false, 1>())
-                           : (col ? width_ok<float, N, true, 1>() : width_ok<float, N, false, 1>());
-        case 2: return dbl ? (col ? width_ok<double, N, true, 2>() : width_ok<double, N, false, 2>())
-                           : (col ? width_ok<float, N, true, 2>() : width_ok<float, N, false, 2>());
+        case 0: return dbl ? (col ? width_ok<double, N, true, 0, V>() : width_ok<double, N, false, 0, V>())
+                           : (col ? width_ok<float, N, true, 0, V>() : width_ok<float, N, false, 0, V>());
+        case 1: return dbl ? (col ? width_ok<double, N, true, 1, V>() : width_ok<double, N, false, 1, V>())
+                           : (col ? width_ok<float, N, true, 1, V>() : width_ok<float, N, false, 1, V>());
+        case 2: return dbl ? (col ? width_ok<double, N, true, 2, V>() : width_ok<double, N, false, 2, V>())
+                           : (col ? width_ok<float, N, true, 2, V>() : width_ok<float, N, false, 2, V>());
         default: return false;
     }
 }
-bool host_width_ok(int n, int w, bool col, bool dbl) {
+template <int N>
+bool host_width_ok_n(int w, int v, bool col, bool dbl) {
+    switch (v) {
+        case 0: return host_width_ok_v<N, 0>(w, col, dbl);
+        case 1: return host_width_ok_v<N, 1>(w, col, dbl);
+        default: return false;
+    }
+}
+bool host_width_ok(int n, int w, int v, bool col, bool dbl) {
     switch (n) {
-#define NSLCT_CASE_W(v) \
-    case v:           \
-        return host_width_ok_n<v>(w, col, dbl);
+#define NSLCT_CASE_W(x) \
+    case x:           \
+        return host_width_ok_n<x>(w, v, col, dbl);
         NSLCT_BATCH_SIZES(NSLCT_CASE_W)
 #undef NSLCT_CASE_W
         default:
             return false;
     }
 }
-int host_width_lines(int n, int w) {
+int host_width_lines(int n, int w, int v) {
     switch (n) {
-#define NSLCT_CASE_L(v) \
-    case v:           \
-        return (256 << w) / LinePlan<v>::TPL;
+#define NSLCT_CASE_L(x) \
+    case x:           \
+        return (256 << w) / (v ? PlanVariant<x, 1>::TPL : PlanVariant<x, 0>::TPL);
         NSLCT_BATCH_SIZES(NSLCT_CASE_L)
 #undef NSLCT_CASE_L
         default:
@@ -118,10 +130,10 @@ int default_width(bool col, bool dbl) { return (col && !dbl) ? 1 : 0; }
 // a multiple of 8); otherwise one workgroup per item, without the loop,
 // whose loop-invariant values would otherwise stay in registers across
 // iterations.
-template <typename T, int N, bool COL, bool LOOP, int W>
-__global__ void __launch_bounds__((width_lines<N, W>() * LinePlan<N>::TPL))
+template <typename T, int N, bool COL, bool LOOP, int W, int V>
+__global__ void __launch_bounds__((width_lines<N, W, V>() * PlanVariant<N, V>::TPL))
     nslct_batched_pass(BatchArgs<T> b, const BatchItem* __restrict__ items, const BatchPass<T>* __restrict__ passes) {
-    constexpr int L = width_lines<N, W>();
+    constexpr int L = width_lines<N, W, V>();
     __shared__ cplx<T> lds[L * lds_line_elems<N>()];
     // The work list and the pass table come in as restrict parameters (no
     // store of the kernel can alias them), so their uniform-index loads are
@@ -133,7 +145,7 @@ __global__ void __launch_bounds__((width_lines<N, W>() * LinePlan<N>::TPL))
             PassArgs<T> a = passes[k].a;
             a.in = b.in;
             a.out = b.out;
-            pass_body<T, N, COL, L>(a, w.tile, (size_t)passes[k].off, lds);
+            pass_body<T, N, COL, L, 1, false, PlanVariant<N, V>>(a, w.tile, (size_t)passes[k].off, lds);
         }
     };
     if constexpr (LOOP) {
@@ -146,15 +158,15 @@ __global__ void __launch_bounds__((width_lines<N, W>() * LinePlan<N>::TPL))
     }
 }
 
-template <typename T, int N, bool COL, int W>
+template <typename T, int N, bool COL, int W, int V>
 hipError_t launch_batched_w(const BatchArgs<T>& a, int grid, hipStream_t s) {
-    if constexpr (width_ok<T, N, COL, W>()) {
-        const dim3 block(width_lines<N, W>() * LinePlan<N>::TPL);
+    if constexpr (width_ok<T, N, COL, W, V>()) {
+        const dim3 block(width_lines<N, W, V>() * PlanVariant<N, V>::TPL);
         if (grid >= a.nitems)
-            hipLaunchKernelGGL((nslct_batched_pass<T, N, COL, false, W>), dim3(a.nitems), block, 0, s, a, a.items,
+            hipLaunchKernelGGL((nslct_batched_pass<T, N, COL, false, W, V>), dim3(a.nitems), block, 0, s, a, a.items,
                                a.passes);
         else
-            hipLaunchKernelGGL((nslct_batched_pass<T, N, COL, true, W>), dim3(grid), block, 0, s, a, a.items,
+            hipLaunchKernelGGL((nslct_batched_pass<T, N, COL, true, W, V>), dim3(grid), block, 0, s, a, a.items,
                                a.passes);
         return hipGetLastError();
     } else {
@@ -162,22 +174,31 @@ hipError_t launch_batched_w(const BatchArgs<T>& a, int grid, hipStream_t s) {
     }
 }
 
-template <typename T, bool COL, int N>
-hipError_t launch_batched_n(int w, const BatchArgs<T>& a, int grid, hipStream_t s) {
+template <typename T, bool COL, int N, int V>
+hipError_t launch_batched_v(int w, const BatchArgs<T>& a, int grid, hipStream_t s) {
     switch (w) {
-        case 0: return launch_batched_w<T, N, COL, 0>(a, grid, s);
-        case 1: return launch_batched_w<T, N, COL, 1>(a, grid, s);
-        case 2: return launch_batched_w<T, N, COL, 2>(a, grid, s);
+        case 0: return launch_batched_w<T, N, COL, 0, V>(a, grid, s);
+        case 1: return launch_batched_w<T, N, COL, 1, V>(a, grid, s);
+        case 2: return launch_batched_w<T, N, COL, 2, V>(a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, bool COL, int N>
+hipError_t launch_batched_n(int v, int w, const BatchArgs<T>& a, int grid, hipStream_t s) {
+    switch (v) {
+        case 0: return launch_batched_v<T, COL, N, 0>(w, a, grid, s);
+        case 1: return launch_batched_v<T, COL, N, 1>(w, a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T, bool COL>
-hipError_t launch_batched_group(int N, int w, const BatchArgs<T>& a, int grid, hipStream_t s) {
+hipError_t launch_batched_group(int N, int v, int w, const BatchArgs<T>& a, int grid, hipStream_t s) {
     switch (N) {
-#define NSLCT_CASE_LAUNCH(v) \
-    case v:                  \
-        return launch_batched_n<T, COL, v>(w, a, grid, s);
+#define NSLCT_CASE_LAUNCH(x) \
+    case x:                  \
+        return launch_batched_n<T, COL, x>(v, w, a, grid, s);
         NSLCT_BATCH_SIZES(NSLCT_CASE_LAUNCH)
 #undef NSLCT_CASE_LAUNCH
         default:
@@ -203,6 +224,7 @@ struct nslct_batch_s {
         int grid;
         BatchItem* items;
         int width;    // tile width index (width_lines)
+        int plan;     // line plan (PlanVariant index)
         int mult;     // persistent workgroups per CU (0: one per item)
         int cached;   // schedule taken from the schedule cache
         double us;    // measured time of one launch of this group while tuning
@@ -249,8 +271,8 @@ hipError_t launch_group_pass(const nslct_batch_s& b, int col, const nslct_batch_
     a.nitems = g.nitems;
     a.dir = dir;
     a.pass = pass;
-    return col ? launch_batched_group<T, true>(g.N, g.width, a, g.grid, st)
-               : launch_batched_group<T, false>(g.N, g.width, a, g.grid, st);
+    return col ? launch_batched_group<T, true>(g.N, g.plan, g.width, a, g.grid, st)
+               : launch_batched_group<T, false>(g.N, g.plan, g.width, a, g.grid, st);
 }
 
 template <typename T>
@@ -333,9 +355,10 @@ void set_grids(nslct_batch_s* b, int mult, int cus) {
         }
 }
 
-// (Re)builds and uploads the work list of group g for tile width w.
-hipError_t set_group_width(nslct_batch_s& b, int col, nslct_batch_s::Group& g, int w) {
-    const std::vector<BatchItem> items = build_items(b, col == 1, g.N, host_width_lines(g.N, w));
+// (Re)builds and uploads the work list of group g for tile width w and
+// line plan v.
+hipError_t set_group_width(nslct_batch_s& b, int col, nslct_batch_s::Group& g, int w, int v) {
+    const std::vector<BatchItem> items = build_items(b, col == 1, g.N, host_width_lines(g.N, w, v));
     if (g.items) {
         hipError_t e = hipFree(g.items);
         g.items = nullptr;
@@ -346,13 +369,15 @@ hipError_t set_group_width(nslct_batch_s& b, int col, nslct_batch_s::Group& g, i
         e = hipMemcpy(g.items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
     g.nitems = (int)items.size();
     g.width = w;
+    g.plan = v;
     return e;
 }
 
 // ------------------------------------------------------------ schedule cache
 // The tuned schedule of a group is kept in a text file, one line per
 //   <gfx arch> <precision> <axis 0 rows / 1 columns> <N> <items, rounded up
-//   to a power of two> <width> <mult> <microseconds>
+//   to a power of two> <line plan> <width> <mult> <microseconds>
+// (lines of any other shape are skipped)
 // (file NSLCT_TUNE_CACHE, default $HOME/.cache/nslct/batch_schedule.txt;
 // NSLCT_TUNE_CACHE=off disables it).  A batch whose groups are all found
 // there is not tuned again.
@@ -377,16 +402,20 @@ int bucket_of(int nitems) {
     return b;
 }
 
-bool cache_lookup(const std::string& path, const CacheKey& k, int* w, int* mult) {
+bool cache_lookup(const std::string& path, const CacheKey& k, int* v, int* w, int* mult) {
     if (path.empty()) return false;
     std::ifstream f(path);
-    std::string arch;
-    int prec, col, N, bucket, ww, mm;
-    double us;
+    std::string line;
     bool found = false;
-    while (f >> arch >> prec >> col >> N >> bucket >> ww >> mm >> us) {
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string arch, extra;
+        int prec, col, N, bucket, vv, ww, mm;
+        double us;
+        if (!(in >> arch >> prec >> col >> N >> bucket >> vv >> ww >> mm >> us) || (in >> extra)) continue;
         if (arch == k.arch && prec == k.prec && col == k.col && N == k.N && bucket == k.bucket) {
-            *w = ww;  // the last entry for a key wins
+            *v = vv;  // the last entry for a key wins
+            *w = ww;
             *mult = mm;
             found = true;
         }
@@ -394,7 +423,7 @@ bool cache_lookup(const std::string& path, const CacheKey& k, int* w, int* mult)
     return found;
 }
 
-void cache_store(const std::string& path, const CacheKey& k, int w, int mult, double us) {
+void cache_store(const std::string& path, const CacheKey& k, int v, int w, int mult, double us) {
     if (path.empty()) return;
     const size_t slash = path.rfind('/');
     if (slash != std::string::npos && slash > 0) {
@@ -404,8 +433,8 @@ void cache_store(const std::string& path, const CacheKey& k, int w, int mult, do
             if (p == dir.size() || dir[p] == '/') (void)mkdir(dir.substr(0, p).c_str(), 0755);
     }
     std::ofstream f(path, std::ios::app);
-    if (f) f << k.arch << ' ' << k.prec << ' ' << k.col << ' ' << k.N << ' ' << k.bucket << ' ' << w << ' '
-             << mult << ' ' << us << '\n';
+    if (f) f << k.arch << ' ' << k.prec << ' ' << k.col << ' ' << k.N << ' ' << k.bucket << ' ' << v << ' ' << w
+             << ' ' << mult << ' ' << us << '\n';
 }
 
 std::string device_arch(int dev) {
@@ -508,8 +537,8 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
         }
         std::sort(sizes.begin(), sizes.end(), std::greater<int>());
         for (int N : sizes) {
-            b->groups[col].push_back({N, 0, 8, nullptr, default_width(col == 1, dbl), 0, 0, 0.0});
-            e = set_group_width(*b, col, b->groups[col].back(), b->groups[col].back().width);
+            b->groups[col].push_back({N, 0, 8, nullptr, default_width(col == 1, dbl), 0, 0, 0, 0.0});
+            e = set_group_width(*b, col, b->groups[col].back(), b->groups[col].back().width, 0);
             if (e != hipSuccess) return batch_fail(b, e, "work list upload");
         }
     }
@@ -551,11 +580,12 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
         std::lock_guard<std::mutex> lk(g_cache_mu);
         for (int col = 0; col < 2; ++col)
             for (auto& g : b->groups[col]) {
-                int w = 0, m = 0;
-                const bool hit = cache_lookup(path, key_of(col, g), &w, &m) && host_width_ok(g.N, w, col == 1, dbl) &&
+                int v = 0, w = 0, m = 0;
+                const bool hit = cache_lookup(path, key_of(col, g), &v, &w, &m) &&
+                                 host_width_ok(g.N, w, v, col == 1, dbl) &&
                                  std::find(std::begin(mults), std::end(mults), m) != std::end(mults);
                 if (hit) {
-                    if (w != g.width) e = set_group_width(*b, col, g, w);
+                    if (w != g.width || v != g.plan) e = set_group_width(*b, col, g, w, v);
                     if (e != hipSuccess) return batch_fail(b, e, "work list upload");
                     g.mult = m;
                     g.grid = grid_for(m, cus, g.nitems);
@@ -580,10 +610,11 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
                 // The heavier pass of the axis (two line DFTs around a chirp).
                 const int pass = col ? 1 : 2;
                 double best = 1e30;
-                int bw = g.width, bm = 0;
+                int bv = g.plan, bw = g.width, bm = 0;
+                for (int v = 0; v < kPlans && e == hipSuccess; ++v)
                 for (int w = 0; w <= kMaxWidth && e == hipSuccess; ++w) {
-                    if (!host_width_ok(g.N, w, col == 1, dbl)) continue;
-                    e = set_group_width(*b, col, g, w);
+                    if (!host_width_ok(g.N, w, v, col == 1, dbl)) continue;
+                    e = set_group_width(*b, col, g, w, v);
                     for (int m : mults) {
                         if (e != hipSuccess) break;
                         g.grid = grid_for(m, cus, g.nitems);
@@ -600,18 +631,19 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
                         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
                         if (e == hipSuccess && ms / 3 * 1e3 < best) {
                             best = ms / 3 * 1e3;
+                            bv = v;
                             bw = w;
                             bm = m;
                         }
                     }
                 }
                 if (e != hipSuccess) break;
-                if (bw != g.width) e = set_group_width(*b, col, g, bw);
+                if (bw != g.width || bv != g.plan) e = set_group_width(*b, col, g, bw, bv);
                 g.mult = bm;
                 g.grid = grid_for(bm, cus, g.nitems);
                 g.us = best;
                 std::lock_guard<std::mutex> lk(g_cache_mu);
-                cache_store(path, key_of(col, g), bw, bm, best);
+                cache_store(path, key_of(col, g), bv, bw, bm, best);
             }
         // The whole batch with the chosen schedule.
         if (e == hipSuccess) e = run_batched(*b, 0, scratch, scratch, b->cap);
@@ -656,13 +688,14 @@ int nslct_batch_set_grid(nslct_batch_t batch, int mult) {
     return NSLCT_OK;
 }
 
-int nslct_batch_group(nslct_batch_t batch, int col, int N, int* lines, int* mult, int* cached) {
+int nslct_batch_group(nslct_batch_t batch, int col, int N, int* plan, int* lines, int* mult, int* cached) {
     if (!batch) return fail(NSLCT_E_ARG, "null batch");
     if (col != 0 && col != 1) return fail(NSLCT_E_ARG, "col must be 0 (rows) or 1 (columns)");
     std::lock_guard<std::mutex> lk(batch->mu);
     for (const auto& g : batch->groups[col])
         if (g.N == N) {
-            if (lines) *lines = host_width_lines(g.N, g.width);
+            if (plan) *plan = g.plan;
+            if (lines) *lines = host_width_lines(g.N, g.width, g.plan);
             if (mult) *mult = g.mult;
             if (cached) *cached = g.cached;
             return NSLCT_OK;
@@ -670,9 +703,10 @@ int nslct_batch_group(nslct_batch_t batch, int col, int N, int* lines, int* mult
     return fail(NSLCT_E_ARG, "no group of that axis and line length in the batch");
 }
 
-int nslct_batch_set_group(nslct_batch_t batch, int col, int N, int lines, int mult) {
+int nslct_batch_set_group(nslct_batch_t batch, int col, int N, int plan, int lines, int mult) {
     if (!batch) return fail(NSLCT_E_ARG, "null batch");
     if (col != 0 && col != 1) return fail(NSLCT_E_ARG, "col must be 0 (rows) or 1 (columns)");
+    if (plan < 0 || plan >= kPlans) return fail(NSLCT_E_ARG, "plan must be 0 or 1");
     if (mult != 0 && mult != 1 && mult != 2 && mult != 4 && mult != 8)
         return fail(NSLCT_E_ARG, "mult must be 0, 1, 2, 4 or 8");
     std::lock_guard<std::mutex> lk(batch->mu);
@@ -680,13 +714,15 @@ int nslct_batch_set_group(nslct_batch_t batch, int col, int N, int lines, int mu
         if (g.N != N) continue;
         int w = -1;
         for (int k = 0; k <= kMaxWidth; ++k)
-            if (host_width_lines(N, k) == lines && host_width_ok(N, k, col == 1, batch->precision == NSLCT_C128)) w = k;
-        if (w < 0) return fail(NSLCT_E_ARG, "not a tile width of this group");
+            if (host_width_lines(N, k, plan) == lines &&
+                host_width_ok(N, k, plan, col == 1, batch->precision == NSLCT_C128))
+                w = k;
+        if (w < 0) return fail(NSLCT_E_ARG, "not a (line plan, tile width) of this group");
         int dev = -1;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess && dev != batch->device) e = hipSetDevice(batch->device);
         if (e == hipSuccess) e = hipDeviceSynchronize();
-        if (e == hipSuccess && w != g.width) e = set_group_width(*batch, col, g, w);
+        if (e == hipSuccess && (w != g.width || plan != g.plan)) e = set_group_width(*batch, col, g, w, plan);
         if (dev >= 0 && dev != batch->device) (void)hipSetDevice(dev);
         if (e != hipSuccess) return fail(NSLCT_E_HIP, std::string("set group: ") + hipGetErrorString(e));
         g.mult = mult;

@@ -318,6 +318,31 @@ struct LinePlan<768> {
     using L = RList<8, 12, 8>;
 };
 
+// Alternative line plans (V = 1) that the ragged batch's schedule tuner
+// times against LinePlan<N> (V = 0): another split of the line over
+// threads and radices, the first and last radix equal and every radix
+// dividing the per-thread sample count, lines still inside one wavefront.
+template <int N, int V>
+struct PlanVariant : LinePlan<N> {
+    static constexpr bool exists = V == 0;
+};
+#define NSLCT_PLAN_VARIANT(n, tpl, ...)           \
+    template <>                                   \
+    struct PlanVariant<n, 1> {                    \
+        static constexpr bool exists = true;      \
+        static constexpr int TPL = tpl;           \
+        using L = RList<__VA_ARGS__>;             \
+    };
+NSLCT_PLAN_VARIANT(64, 16, 4, 4, 4)
+NSLCT_PLAN_VARIANT(128, 8, 8, 2, 8)
+NSLCT_PLAN_VARIANT(192, 16, 4, 12, 4)
+NSLCT_PLAN_VARIANT(256, 32, 8, 4, 8)
+NSLCT_PLAN_VARIANT(384, 32, 4, 6, 4, 4)
+NSLCT_PLAN_VARIANT(512, 32, 16, 2, 16)
+NSLCT_PLAN_VARIANT(768, 64, 4, 12, 4, 4)
+NSLCT_PLAN_VARIANT(1024, 32, 16, 4, 16)
+#undef NSLCT_PLAN_VARIANT
+
 // LDS index of line position p (one padding element every 16).
 __device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
 template <int N>
@@ -337,7 +362,7 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T, int N, int TPL>
+template <typename T, int N, int TPL, typename PL = typename LinePlan<N>::L>
 struct LineFFT {
     static constexpr int E = N / TPL;
     // A line owned by at most one wavefront synchronises at wavefront scope.
@@ -369,7 +394,7 @@ struct LineFFT {
     static constexpr int tw_total(RList<R...>) {
         return tw_count<1, R...>();
     }
-    static constexpr int TW = tw_total(typename LinePlan<N>::L{}) > 0 ? tw_total(typename LinePlan<N>::L{}) : 1;
+    static constexpr int TW = tw_total(PL{}) > 0 ? tw_total(PL{}) : 1;
 
     template <int Ns, int R, int... Rest>
     __device__ __forceinline__ static void preload_from(cplx<T>* w, int off, int t, const cplx<T>* __restrict__ tab) {
@@ -389,7 +414,7 @@ struct LineFFT {
     }
     // Loads this thread's register twiddles (forward sign) for all stages.
     __device__ __forceinline__ static void preload(cplx<T>* w, int t, const cplx<T>* __restrict__ tab) {
-        preload_list(typename LinePlan<N>::L{}, w, t, tab);
+        preload_list(PL{}, w, t, tab);
     }
 
     // One Stockham stage (twiddles + radix-R butterflies) on the registers.
@@ -493,7 +518,7 @@ struct LineFFT {
     template <int S>
     __device__ __forceinline__ static void dft(cplx<T>* v, cplx<T>* lds, int t, const cplx<T>* w,
                                                const cplx<T>* __restrict__ tab) {
-        run<S>(typename LinePlan<N>::L{}, v, lds, t, w, tab);
+        run<S>(PL{}, v, lds, t, w, tab);
     }
 
     template <int... R>
@@ -504,8 +529,8 @@ struct LineFFT {
     static constexpr int last_radix(RList<R...>) {
         return LastOf<R...>::value;
     }
-    static constexpr int R0 = first_radix(typename LinePlan<N>::L{});
-    static_assert(R0 == last_radix(typename LinePlan<N>::L{}), "first and last radix must match");
+    static constexpr int R0 = first_radix(PL{});
+    static_assert(R0 == last_radix(PL{}), "first and last radix must match");
     static_assert(E % R0 == 0, "bad line plan");
     static_assert(R0 % 2 == 0, "the chirp index split assumes an even first radix");
 };

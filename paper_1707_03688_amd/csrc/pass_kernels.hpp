@@ -137,10 +137,10 @@ __device__ __forceinline__ int store_to_fft(int p) {
 // longer than a wavefront, their loads) are staged through LDS so that the
 // global accesses cover LINES consecutive samples of each row (coalesced),
 // while each line's FFT work stays with the TPL threads that own it.
-template <typename T, int N, bool COL, int LINES, int NS = 1, bool X3 = false>
+template <typename T, int N, bool COL, int LINES, int NS = 1, bool X3 = false, typename PP = LinePlan<N>>
 __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t img_off, cplx<T>* lds_all) {
-    constexpr int TPL = LinePlan<N>::TPL;
-    using F = LineFFT<T, N, TPL>;
+    constexpr int TPL = PP::TPL;
+    using F = LineFFT<T, N, TPL, typename PP::L>;
     constexpr int E = F::E;
     constexpr int R0 = F::R0;
     constexpr int LL = lds_line_elems<N>();
