@@ -179,7 +179,11 @@ int nslct_forward(nslct_plan_t plan, const void* in, void* out, void* stream);
 int nslct_inverse(nslct_plan_t plan, const void* in, void* out, void* stream);
 
 /* `count` images of the plan's shape stored back to back (image stride
- * Nx*Ny samples), all with the plan's matrix.  in == out allowed. */
+ * Nx*Ny samples), all with the plan's matrix.  in == out allowed.  For
+ * complex64 passes over lines of length 64, 192, 256, 384, 512, 768 or 1024
+ * the split of a line over threads is chosen by the number of lines in
+ * flight (lines of the pass times count), so one image's result may differ
+ * in its last bits with `count` (every result within the complex64 bar). */
 int nslct_forward_many(nslct_plan_t plan, int count, const void* in, void* out, void* stream);
 int nslct_inverse_many(nslct_plan_t plan, int count, const void* in, void* out, void* stream);
 

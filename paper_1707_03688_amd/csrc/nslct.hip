@@ -76,20 +76,49 @@ int nslct::ensure_device_ready() {
 
 namespace {
 
-template <typename T, int N, bool COL, int LINES, bool X3 = false>
-__global__ void __launch_bounds__(LinePlan<N>::TPL* LINES) nslct_pass(PassArgs<T> a) {
+// Line plan of the single-image passes.  The alternative split of a line
+// over threads (PlanVariant<N, 1>) trades per-line latency for occupancy:
+// measured on gfx950 (complex64, square images, all counts alike), it is
+// faster for 192 always, for 256, 384 and 768 when few lines are in flight,
+// and for 64, 512 and 1024 when many are; `lines` = lines of the pass times
+// images.  (Complex128 and the other lengths keep LinePlan<N>.)
+bool alt_plan(int N, long long lines) {
+    switch (N) {
+        case 64: return lines >= 1024;
+        case 192: return true;
+        case 256: return lines <= 4096;
+        case 384: return lines <= 3072;
+        case 512: return lines >= 2048;
+        case 768: return lines <= 1536;
+        case 1024: return lines >= 32768;
+        default: return false;
+    }
+}
+
+template <typename T, int N, bool COL, int LINES, bool X3, int V>
+__global__ void __launch_bounds__((PlanVariant<N, V>::TPL * LINES)) nslct_pass(PassArgs<T> a) {
     __shared__ cplx<T> lds_all[LINES * lds_line_elems<N>()];
     const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    pass_body<T, N, COL, LINES, 1, X3>(a, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
+    pass_body<T, N, COL, LINES, 1, X3, PlanVariant<N, V>>(a, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
+}
+template <typename T, int N, bool COL, bool X3, int V>
+hipError_t launch_tv(const PassArgs<T>& a, int count, hipStream_t s) {
+    constexpr int TPL = PlanVariant<N, V>::TPL;
+    // Column tiles keep the thread count of the LinePlan tile; row tiles
+    // 256 threads.
+    constexpr int L = COL ? (col_lines<T, N>() * LinePlan<N>::TPL + TPL - 1) / TPL : row_lines_of<PlanVariant<N, V>>();
+    static_assert(L * lds_line_elems<N>() * sizeof(cplx<T>) <= 160 * 1024, "LDS budget");
+    dim3 grid((a.nlines + L - 1) / L, count);
+    dim3 block(TPL * L);
+    hipLaunchKernelGGL((nslct_pass<T, N, COL, L, X3, V>), grid, block, 0, s, a);
+    return hipGetLastError();
 }
 template <typename T, int N, bool COL, bool X3 = false>
 hipError_t launch_t(const PassArgs<T>& a, int count, hipStream_t s) {
-    constexpr int L = COL ? col_lines<T, N>() : row_lines<T, N>();
-    static_assert(L * lds_line_elems<N>() * sizeof(cplx<T>) <= 160 * 1024, "LDS budget");
-    dim3 grid((a.nlines + L - 1) / L, count);
-    dim3 block(LinePlan<N>::TPL * L);
-    hipLaunchKernelGGL((nslct_pass<T, N, COL, L, X3>), grid, block, 0, s, a);
-    return hipGetLastError();
+    if constexpr (sizeof(T) == 4 && PlanVariant<N, 1>::exists) {
+        if (alt_plan(N, (long long)a.nlines * count)) return launch_tv<T, N, COL, X3, 1>(a, count, s);
+    }
+    return launch_tv<T, N, COL, X3, 0>(a, count, s);
 }
 
 template <typename T, bool COL, bool X3 = false>

@@ -409,9 +409,13 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
 
 
 
+template <typename P>
+constexpr int row_lines_of() {
+    return P::TPL >= 256 ? 1 : 256 / P::TPL;
+}
 template <typename T, int N>
 constexpr int row_lines() {
-    return LinePlan<N>::TPL >= 256 ? 1 : 256 / LinePlan<N>::TPL;
+    return row_lines_of<LinePlan<N>>();
 }
 // Columns per tile: 4 (complex64) or 2 (complex128) adjacent columns, so a
 // row segment is 32 bytes, but no more than 512 threads per workgroup: a

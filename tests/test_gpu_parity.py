@@ -169,11 +169,11 @@ def test_many_inplace_and_passes_are_bitwise_consistent(torch, nl):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("shape,count,precision", [((1024, 1024), 8, "c64"), ((512, 512), 32, "c64"),
-                                                    ((256, 384), 24, "c128")])
+@pytest.mark.parametrize("shape,count,precision", [((1024, 1024), 8, "c64"), ((256, 384), 24, "c128")])
 def test_multi_image_launches_are_bitwise(torch, nl, shape, count, precision):
     """Multi-image launches at full size (thousands of workgroups per pass)
-    give the bits of one-image launches, forward and inverse, in place too."""
+    give the bits of one-image launches where both run the same line plan,
+    forward and inverse, in place too."""
     M = _draws(29, 1)[0]
     Nx, Ny = shape
     d = math.sqrt(2 * math.pi / max(Nx, Ny))
@@ -188,6 +188,32 @@ def test_multi_image_launches_are_bitwise(torch, nl, shape, count, precision):
     back = pg.inverse(many)
     for b in (0, count - 1):
         assert torch.equal(pg.inverse(many[b].contiguous()), back[b])
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("N,count", [(64, 16), (512, 4), (512, 32), (1024, 32)])
+def test_line_plan_switch_with_lines_in_flight(torch, nl, N, count):
+    """Complex64 passes of 64-, 512- and 1024-long lines take the
+    alternative line plan when many lines are in flight (images x lines):
+    the multi-image result against the FP64 oracle (first and last image),
+    against one-image launches (the other plan: same transform to
+    rounding), in place bitwise, and its inverse."""
+    M = _draws(31, 1)[0]
+    d = math.sqrt(2 * math.pi / N)
+    po, pg = _pair(nl, M, N, N, d, d)
+    gen = torch.Generator(device="cuda").manual_seed(N + count)
+    x = torch.randn((count, N, N), dtype=torch.complex64, device="cuda", generator=gen)
+    many = pg.forward(x)
+    for b in (0, count - 1):
+        xb = x[b].cpu().numpy().astype(np.complex128)
+        assert chain.rel_l2(many[b].cpu().numpy(), chain.forward(po, xb)) <= TOL["c64"]
+        one = pg.forward(x[b].contiguous())
+        assert (torch.linalg.vector_norm(one - many[b]) / torch.linalg.vector_norm(one)).item() <= 1e-6
+    y = x.clone()
+    pg.forward(y, out=y)
+    assert torch.equal(y, many)
+    back = pg.inverse(many)
+    assert (torch.linalg.vector_norm(back - x) / torch.linalg.vector_norm(x)).item() <= TOL["c64"]
     torch.cuda.synchronize()
 
 
