@@ -17,11 +17,11 @@ namespace {
 
 // Backward sweep: the inverse chain applied to the forward output G and to
 // the incoming gradient at once, with the gradient sums at every chirp point.
-template <typename T, int N, bool COL, int LINES>
-__global__ void __launch_bounds__(LinePlan<N>::TPL* LINES) nslct_pair_pass(PassArgs<T> a) {
+template <typename T, int N, bool COL, int LINES, int V>
+__global__ void __launch_bounds__((PlanVariant<N, V>::TPL * LINES)) nslct_pair_pass(PassArgs<T> a) {
     __shared__ cplx<T> lds_all[LINES * lds_line_elems<N>()];
     const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    pass_body<T, N, COL, LINES, 2>(a, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
+    pass_body<T, N, COL, LINES, 2, false, PlanVariant<N, V>>(a, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
 }
 
 #define NSLCT_PAIR_SIZES(X) X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
@@ -37,16 +37,24 @@ bool pair_size_ok(int n) {
     }
 }
 
+template <typename T, int N, bool COL, int V>
+hipError_t launch_pair_v(const PassArgs<T>& a, int count, hipStream_t s) {
+    constexpr int TPL = PlanVariant<N, V>::TPL;
+    constexpr int L = COL ? (col_lines<T, N>() * LinePlan<N>::TPL + TPL - 1) / TPL : row_lines_of<PlanVariant<N, V>>();
+    hipLaunchKernelGGL((nslct_pair_pass<T, N, COL, L, V>), dim3((a.nlines + L - 1) / L, count), dim3(TPL * L), 0, s,
+                       a);
+    return hipGetLastError();
+}
+
 template <typename T, bool COL>
-hipError_t launch_pair_n(int N, const PassArgs<T>& a, int count, hipStream_t s) {
+hipError_t launch_pair_n(int N, const PassArgs<T>& a, int count, int plan_count, hipStream_t s) {
     switch (N) {
-#define NSLCT_PAIR_LAUNCH(v)                                                                     \
-    case v: {                                                                                    \
-        constexpr int L = COL ? col_lines<T, v>() : row_lines<T, v>();                           \
-        hipLaunchKernelGGL((nslct_pair_pass<T, v, COL, L>), dim3((a.nlines + L - 1) / L, count), \
-                           dim3(LinePlan<v>::TPL * L), 0, s, a);                                 \
-        return hipGetLastError();                                                                \
-    }
+#define NSLCT_PAIR_LAUNCH(v)                                                                   \
+    case v:                                                                                    \
+        if constexpr (sizeof(T) == 4 && PlanVariant<v, 1>::exists)                             \
+            if (v != 1024 && alt_plan(v, (long long)a.nlines * plan_count))                   \
+                return launch_pair_v<T, v, COL, 1>(a, count, s);                               \
+        return launch_pair_v<T, v, COL, 0>(a, count, s);
         NSLCT_PAIR_SIZES(NSLCT_PAIR_LAUNCH)
 #undef NSLCT_PAIR_LAUNCH
         default:
@@ -55,7 +63,7 @@ hipError_t launch_pair_n(int N, const PassArgs<T>& a, int count, hipStream_t s) 
 }
 
 template <typename T>
-hipError_t run_backward_t(const PlanData& d, int count, const void* G, const void* gout, void* work, void* gx,
+hipError_t run_backward_t(const PlanData& d, int count, int plan_count, const void* G, const void* gout, void* work, void* gx,
                           double* sums, hipStream_t s) {
     for (int pass = 0; pass < 5; ++pass) {
         PassArgs<T> a = pass_args<T>(d, 1, pass, pass == 0 ? G : work, work);
@@ -63,7 +71,8 @@ hipError_t run_backward_t(const PlanData& d, int count, const void* G, const voi
         a.out2 = (cplx<T>*)gx;
         a.acc = sums + 3 * pass;
         const bool col = (pass == 1 || pass == 3);
-        const hipError_t e = col ? launch_pair_n<T, true>(d.Nx, a, count, s) : launch_pair_n<T, false>(d.Ny, a, count, s);
+        const hipError_t e = col ? launch_pair_n<T, true>(d.Nx, a, count, plan_count, s)
+                                 : launch_pair_n<T, false>(d.Ny, a, count, plan_count, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -105,7 +114,9 @@ int plan_jac(nslct_plan_t plan, const double** jac) {
 
 // The paired sweep of `count` images through a work image region of `chunk`
 // images (work holds chunk images; the images are processed chunk by
-// chunk), accumulating into the device sums[15] (cleared here first).
+// chunk), accumulating into the device sums[15] (cleared here first).  The
+// line plan of the passes follows `count` (the images of the call), so a
+// chunked sweep computes every image with the same code as a whole one.
 hipError_t sweep_chunks(const PlanData& d, int count, int chunk, const void* G, const void* gout, void* work,
                         void* gx, double* sums, hipStream_t s) {
     hipLaunchKernelGGL(zero_f64, dim3(1), dim3(64), 0, s, sums, 15);
@@ -117,8 +128,8 @@ hipError_t sweep_chunks(const PlanData& d, int count, int chunk, const void* G, 
         const char* g = (const char*)G + i0 * img;
         const char* go = (const char*)gout + i0 * img;
         char* x = (char*)gx + i0 * img;
-        e = d.precision == NSLCT_C128 ? run_backward_t<double>(d, n, g, go, work, x, sums, s)
-                                      : run_backward_t<float>(d, n, g, go, work, x, sums, s);
+        e = d.precision == NSLCT_C128 ? run_backward_t<double>(d, n, count, g, go, work, x, sums, s)
+                                      : run_backward_t<float>(d, n, count, g, go, work, x, sums, s);
     }
     return e;
 }
@@ -182,8 +193,8 @@ int nslct_backward(nslct_plan_t plan, int count, const void* G, const void* grad
     rc = ensure_device_ready();
     if (rc) return rc;
     const hipError_t e = d.precision == NSLCT_C128
-                             ? run_backward_t<double>(d, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream)
-                             : run_backward_t<float>(d, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream);
+                             ? run_backward_t<double>(d, count, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream)
+                             : run_backward_t<float>(d, count, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream);
     return e == hipSuccess ? NSLCT_OK : fail(NSLCT_E_HIP, std::string("backward launch: ") + hipGetErrorString(e));
 }
 

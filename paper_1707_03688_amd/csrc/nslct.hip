@@ -76,25 +76,6 @@ int nslct::ensure_device_ready() {
 
 namespace {
 
-// Line plan of the single-image passes.  The alternative split of a line
-// over threads (PlanVariant<N, 1>) trades per-line latency for occupancy:
-// measured on gfx950 (complex64, square images, all counts alike), it is
-// faster for 192 always, for 256, 384 and 768 when few lines are in flight,
-// and for 64, 512 and 1024 when many are; `lines` = lines of the pass times
-// images.  (Complex128 and the other lengths keep LinePlan<N>.)
-bool alt_plan(int N, long long lines) {
-    switch (N) {
-        case 64: return lines >= 1024;
-        case 192: return true;
-        case 256: return lines <= 4096;
-        case 384: return lines <= 3072;
-        case 512: return lines >= 2048;
-        case 768: return lines <= 1536;
-        case 1024: return lines >= 32768;
-        default: return false;
-    }
-}
-
 template <typename T, int N, bool COL, int LINES, bool X3, int V>
 __global__ void __launch_bounds__((PlanVariant<N, V>::TPL * LINES)) nslct_pass(PassArgs<T> a) {
     __shared__ cplx<T> lds_all[LINES * lds_line_elems<N>()];

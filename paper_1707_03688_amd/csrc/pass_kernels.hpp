@@ -409,6 +409,27 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
 
 
 
+// Line plan of the single-image passes.  The alternative split of a line
+// over threads (PlanVariant<N, 1>) trades per-line latency for occupancy:
+// measured on gfx950 (complex64, square images, all counts alike), it is
+// faster for 192 always, for 256, 384 and 768 when few lines are in flight,
+// and for 64, 512 and 1024 when many are; `lines` = lines of the pass times
+// images.  (Complex128 and the other lengths keep LinePlan<N>.)  The
+// backward sweep's paired passes follow the same rule except at 1024, where
+// their two signals make the alternative slower at every count measured.
+inline bool alt_plan(int N, long long lines) {
+    switch (N) {
+        case 64: return lines >= 1024;
+        case 192: return true;
+        case 256: return lines <= 4096;
+        case 384: return lines <= 3072;
+        case 512: return lines >= 2048;
+        case 768: return lines <= 1536;
+        case 1024: return lines >= 32768;
+        default: return false;
+    }
+}
+
 template <typename P>
 constexpr int row_lines_of() {
     return P::TPL >= 256 ? 1 : 256 / P::TPL;

@@ -1,7 +1,7 @@
 """GPU test of nslct_backward_theta_noalloc, the allocation-free backward
 entry point (static device scratch): its gradients equal those of
-nslct_backward_theta on the same inputs, on two workloads in a row (the
-second smaller), and after the device's one-time set-up a call takes no
+nslct_backward_theta on the same inputs, on three workloads in a row (each
+smaller than the one before), and after the device's one-time set-up a call takes no
 device memory."""
 from __future__ import annotations
 
@@ -35,7 +35,9 @@ def _call(nl, fn, plan, G, g, gx):
 
 def test_noalloc_backward_matches_allocating_entry_point(torch):
     import paper_1707_03688_amd as nl
-    cases = [(512, 512, "c64", 20, 5), (256, 128, "c128", 3, 6)]  # 40 MiB (3 chunks), then 1.5 MiB
+    # 40 MiB (3 chunks); 9 images (chunks of 8 and 1: the line plan follows
+    # the call's 9 images, not the chunk's); then 1.5 MiB.
+    cases = [(512, 512, "c64", 20, 5), (512, 512, "c64", 9, 7), (256, 128, "c128", 3, 6)]
     for Nx, Ny, prec, count, seed in cases:
         print(f"no-alloc backward: {count} x {Nx} x {Ny} {prec}", flush=True)
         dt = torch.complex64 if prec == "c64" else torch.complex128
