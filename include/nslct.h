@@ -48,8 +48,8 @@
  *   on a power-of-two line of at least 2N - 1 samples (about four times the
  *   arithmetic; its tables are computed on the host and uploaded on the
  *   first transform of that length on a device, so that first call must not
- *   be inside a stream capture).  The batch, backward and split-precision
- *   entry points take native lengths only.
+ *   be inside a stream capture).  The ragged batch takes them too; the
+ *   backward and split-precision entry points take native lengths only.
  */
 #ifndef NSLCT_H
 #define NSLCT_H
@@ -204,7 +204,9 @@ int nslct_plan_passes(nslct_plan_t plan, int* npasses);
 /* Ragged batch: `count` plans (each with its own matrix and size) over one
  * packed buffer in which image i occupies samples [off_i, off_i + Nx_i Ny_i),
  * off_0 = 0, images back to back in plan order.  All plans must share one
- * precision; sides must be 64, 128, 192, 256, 384, 512, 768 or 1024.  The
+ * precision (complex64 or complex128); sides must be 64, 128, 192, 256, 384,
+ * 512, 768, 1024, or any length up to 2048 without a native plan (Bluestein
+ * line DFTs, as in the single-image path; their tables are made here).  The
  * batch copies the plans (they may be destroyed afterwards), uploads a
  * table of pass arguments per (image, direction, pass) and an XCD-balanced
  * work list to the current device.  Its passes run one launch per group

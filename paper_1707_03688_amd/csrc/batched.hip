@@ -18,6 +18,7 @@
 
 #include "internal.hpp"
 #include "pass_kernels.hpp"
+#include "bluestein.hpp"
 
 using namespace nslct;
 
@@ -66,7 +67,7 @@ constexpr bool width_ok() {
            width_lines<N, W, V>() * lds_line_elems<N>() * (int)sizeof(cplx<T>) <= 160 * 1024;
 }
 
-bool batch_size_ok(int n) {
+bool batch_native_size(int n) {
     switch (n) {
 #define NSLCT_CASE_OK(v) case v:
         NSLCT_BATCH_SIZES(NSLCT_CASE_OK)
@@ -74,6 +75,29 @@ bool batch_size_ok(int n) {
         return true;
         default:
             return false;
+    }
+}
+// Sides the batch takes: the native ones above, and every length up to 2048
+// without a native plan (Bluestein line DFTs on M-point lines).
+bool batch_size_ok(int n) { return batch_native_size(n) || (n >= 2 && n <= 2048 && !native_line(n)); }
+
+// Lines per work item of a Bluestein group: the single-image tile of the
+// M-point line.
+template <typename T, int M, bool COL>
+constexpr int bs_lines() {
+    return COL ? col_lines<T, M>() : row_lines<T, M>();
+}
+int host_bs_lines(int M, bool col, bool dbl) {
+    switch (M) {
+#define NSLCT_CASE_BSL(m)                                                                              \
+    case m:                                                                                            \
+        return dbl ? (col ? bs_lines<double, m, true>() : bs_lines<double, m, false>())                \
+                   : (col ? bs_lines<float, m, true>() : bs_lines<float, m, false>());
+        NSLCT_CASE_BSL(8) NSLCT_CASE_BSL(16) NSLCT_CASE_BSL(32) NSLCT_CASE_BSL(64) NSLCT_CASE_BSL(128)
+        NSLCT_CASE_BSL(256) NSLCT_CASE_BSL(512) NSLCT_CASE_BSL(1024) NSLCT_CASE_BSL(2048) NSLCT_CASE_BSL(4096)
+#undef NSLCT_CASE_BSL
+        default:
+            return 1;
     }
 }
 
@@ -158,6 +182,64 @@ __global__ void __launch_bounds__((width_lines<N, W, V>() * PlanVariant<N, V>::T
     }
 }
 
+// Batched Bluestein pass over the images of one non-native line length
+// (all of one M): the same work list and grids as nslct_batched_pass, each
+// item through the single-image Bluestein body.
+template <typename T, int M, bool COL, bool LOOP>
+__global__ void __launch_bounds__((bs_lines<T, M, COL>() * LinePlan<M>::TPL))
+    nslct_batched_bs_pass(BatchArgs<T> b, const BatchItem* __restrict__ items, const BatchPass<T>* __restrict__ passes,
+                          BsArgs<T> bs) {
+    constexpr int L = bs_lines<T, M, COL>();
+    __shared__ cplx<T> lds[L * lds_line_elems<M>()];
+    auto item = [&](int it) {
+        const BatchItem w = items[it];
+        if (w.img >= 0) {
+            const int k = (w.img * 2 + b.dir) * 5 + b.pass;
+            PassArgs<T> a = passes[k].a;
+            a.in = b.in;
+            a.out = b.out;
+            bs_body<T, M, COL, L>(a, bs, w.tile, (size_t)passes[k].off, lds);
+        }
+    };
+    if constexpr (LOOP) {
+        for (int it = blockIdx.x; it < b.nitems; it += gridDim.x) {
+            item(it);
+            __syncthreads();
+        }
+    } else {
+        if ((int)blockIdx.x < b.nitems) item(blockIdx.x);
+    }
+}
+
+template <typename T, int M, bool COL>
+hipError_t launch_batched_bs_m(const BatchArgs<T>& a, const BsArgs<T>& bs, int grid, hipStream_t s) {
+    const dim3 block(bs_lines<T, M, COL>() * LinePlan<M>::TPL);
+    if (grid >= a.nitems)
+        hipLaunchKernelGGL((nslct_batched_bs_pass<T, M, COL, false>), dim3(a.nitems), block, 0, s, a, a.items,
+                           a.passes, bs);
+    else
+        hipLaunchKernelGGL((nslct_batched_bs_pass<T, M, COL, true>), dim3(grid), block, 0, s, a, a.items, a.passes,
+                           bs);
+    return hipGetLastError();
+}
+
+template <typename T, bool COL>
+hipError_t launch_batched_bs(int M, const BatchArgs<T>& a, const BsArgs<T>& bs, int grid, hipStream_t s) {
+    switch (M) {
+        case 8: return launch_batched_bs_m<T, 8, COL>(a, bs, grid, s);
+        case 16: return launch_batched_bs_m<T, 16, COL>(a, bs, grid, s);
+        case 32: return launch_batched_bs_m<T, 32, COL>(a, bs, grid, s);
+        case 64: return launch_batched_bs_m<T, 64, COL>(a, bs, grid, s);
+        case 128: return launch_batched_bs_m<T, 128, COL>(a, bs, grid, s);
+        case 256: return launch_batched_bs_m<T, 256, COL>(a, bs, grid, s);
+        case 512: return launch_batched_bs_m<T, 512, COL>(a, bs, grid, s);
+        case 1024: return launch_batched_bs_m<T, 1024, COL>(a, bs, grid, s);
+        case 2048: return launch_batched_bs_m<T, 2048, COL>(a, bs, grid, s);
+        case 4096: return launch_batched_bs_m<T, 4096, COL>(a, bs, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T, int N, bool COL, int W, int V>
 hipError_t launch_batched_w(const BatchArgs<T>& a, int grid, hipStream_t s) {
     if constexpr (width_ok<T, N, COL, W, V>()) {
@@ -225,6 +307,8 @@ struct nslct_batch_s {
         BatchItem* items;
         int width;    // tile width index (width_lines)
         int plan;     // line plan (PlanVariant index)
+        int M;        // Bluestein line length (0: native N)
+        const void* bs_tab;  // Bluestein table of N (device)
         int mult;     // persistent workgroups per CU (0: one per item)
         int cached;   // schedule taken from the schedule cache
         double us;    // measured time of one launch of this group while tuning
@@ -271,6 +355,10 @@ hipError_t launch_group_pass(const nslct_batch_s& b, int col, const nslct_batch_
     a.nitems = g.nitems;
     a.dir = dir;
     a.pass = pass;
+    if (g.M) {
+        const BsArgs<T> bs{g.N, (const cplx<T>*)g.bs_tab};
+        return col ? launch_batched_bs<T, true>(g.M, a, bs, g.grid, st) : launch_batched_bs<T, false>(g.M, a, bs, g.grid, st);
+    }
     return col ? launch_batched_group<T, true>(g.N, g.plan, g.width, a, g.grid, st)
                : launch_batched_group<T, false>(g.N, g.plan, g.width, a, g.grid, st);
 }
@@ -340,6 +428,15 @@ std::vector<BatchItem> build_items(const nslct_batch_s& b, bool col, int N, int 
     return items;
 }
 
+// (w, v) is a schedule candidate of group g: for a Bluestein group only its
+// single tile (w = 0, v = 0).
+bool candidate_ok(const nslct_batch_s::Group& g, int w, int v, bool col, bool dbl) {
+    return g.M ? (w == 0 && v == 0) : host_width_ok(g.N, w, v, col, dbl);
+}
+int group_lines(const nslct_batch_s::Group& g, bool col, bool dbl) {
+    return g.M ? host_bs_lines(g.M, col, dbl) : host_width_lines(g.N, g.width, g.plan);
+}
+
 int grid_for(int mult, int cus, int nitems) {
     const int want = mult == 0 ? nitems : ((mult * cus + 7) / 8) * 8;
     return std::max(8, std::min(want, nitems));
@@ -358,7 +455,8 @@ void set_grids(nslct_batch_s* b, int mult, int cus) {
 // (Re)builds and uploads the work list of group g for tile width w and
 // line plan v.
 hipError_t set_group_width(nslct_batch_s& b, int col, nslct_batch_s::Group& g, int w, int v) {
-    const std::vector<BatchItem> items = build_items(b, col == 1, g.N, host_width_lines(g.N, w, v));
+    const int L = g.M ? host_bs_lines(g.M, col == 1, b.precision == NSLCT_C128) : host_width_lines(g.N, w, v);
+    const std::vector<BatchItem> items = build_items(b, col == 1, g.N, L);
     if (g.items) {
         hipError_t e = hipFree(g.items);
         g.items = nullptr;
@@ -509,7 +607,7 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
         }
         if (!batch_size_ok(d.Nx) || !batch_size_ok(d.Ny)) {
             delete b;
-            return fail(NSLCT_E_SIZE, "batched sides must be one of 64, 128, 192, 256, 384, 512, 768, 1024");
+            return fail(NSLCT_E_SIZE, "batched sides must be 64, 128, 192, 256, 384, 512, 768, 1024 or a length up to 2048 without a native plan");
         }
         if (d.st.type == 7) {
             delete b;
@@ -537,7 +635,20 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
         }
         std::sort(sizes.begin(), sizes.end(), std::greater<int>());
         for (int N : sizes) {
-            b->groups[col].push_back({N, 0, 8, nullptr, default_width(col == 1, dbl), 0, 0, 0, 0.0});
+            nslct_batch_s::Group g{};
+            g.N = N;
+            g.grid = 8;
+            if (!batch_native_size(N)) {  // Bluestein group: its table on this device
+                g.M = bluestein_length(N);
+                rc = bs_tables(N, g.M, dbl, &g.bs_tab);
+                if (rc) {
+                    delete b;
+                    return rc;
+                }
+            } else {
+                g.width = default_width(col == 1, dbl);
+            }
+            b->groups[col].push_back(g);
             e = set_group_width(*b, col, b->groups[col].back(), b->groups[col].back().width, 0);
             if (e != hipSuccess) return batch_fail(b, e, "work list upload");
         }
@@ -582,7 +693,7 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
             for (auto& g : b->groups[col]) {
                 int v = 0, w = 0, m = 0;
                 const bool hit = cache_lookup(path, key_of(col, g), &v, &w, &m) &&
-                                 host_width_ok(g.N, w, v, col == 1, dbl) &&
+                                 candidate_ok(g, w, v, col == 1, dbl) &&
                                  std::find(std::begin(mults), std::end(mults), m) != std::end(mults);
                 if (hit) {
                     if (w != g.width || v != g.plan) e = set_group_width(*b, col, g, w, v);
@@ -613,7 +724,7 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
                 int bv = g.plan, bw = g.width, bm = 0;
                 for (int v = 0; v < kPlans && e == hipSuccess; ++v)
                 for (int w = 0; w <= kMaxWidth && e == hipSuccess; ++w) {
-                    if (!host_width_ok(g.N, w, v, col == 1, dbl)) continue;
+                    if (!candidate_ok(g, w, v, col == 1, dbl)) continue;
                     e = set_group_width(*b, col, g, w, v);
                     for (int m : mults) {
                         if (e != hipSuccess) break;
@@ -695,7 +806,7 @@ int nslct_batch_group(nslct_batch_t batch, int col, int N, int* plan, int* lines
     for (const auto& g : batch->groups[col])
         if (g.N == N) {
             if (plan) *plan = g.plan;
-            if (lines) *lines = host_width_lines(g.N, g.width, g.plan);
+            if (lines) *lines = group_lines(g, col == 1, batch->precision == NSLCT_C128);
             if (mult) *mult = g.mult;
             if (cached) *cached = g.cached;
             return NSLCT_OK;
@@ -712,10 +823,11 @@ int nslct_batch_set_group(nslct_batch_t batch, int col, int N, int plan, int lin
     std::lock_guard<std::mutex> lk(batch->mu);
     for (auto& g : batch->groups[col]) {
         if (g.N != N) continue;
+        const bool dbl = batch->precision == NSLCT_C128;
         int w = -1;
         for (int k = 0; k <= kMaxWidth; ++k)
-            if (host_width_lines(N, k, plan) == lines &&
-                host_width_ok(N, k, plan, col == 1, batch->precision == NSLCT_C128))
+            if (candidate_ok(g, k, plan, col == 1, dbl) &&
+                (g.M ? host_bs_lines(g.M, col == 1, dbl) : host_width_lines(N, k, plan)) == lines)
                 w = k;
         if (w < 0) return fail(NSLCT_E_ARG, "not a (line plan, tile width) of this group");
         int dev = -1;
@@ -748,7 +860,7 @@ int nslct_batch_run(nslct_batch_t batch, int direction, int mode, const void* in
         for (int i = 0; i < batch->count; ++i) {
             const char* pi = (const char*)in + batch->offsets[i] * es;
             char* po = (char*)out + batch->offsets[i] * es;
-            rc = run_chain(&batch->plans[i], direction, 1, pi, po, stream);
+            rc = run_chain(&batch->plans[i], direction, 1, pi, po, stream, true);
             if (rc) return rc;
         }
         return NSLCT_OK;

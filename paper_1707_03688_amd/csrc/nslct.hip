@@ -36,6 +36,7 @@
 
 #include "internal.hpp"
 #include "pass_kernels.hpp"
+#include "bluestein.hpp"
 
 using namespace nslct;
 
@@ -299,22 +300,12 @@ hipError_t launch_col4096(const PassArgs<T>& a, int count, hipStream_t s) {
 template <typename T>
 hipError_t launch_pass_typed(const PlanData& d, int dir, int pass, int count, const void* in, void* out,
                              hipStream_t s);
+}  // namespace
+
 // ---------------------------------------------------------------- Bluestein
-// Line lengths N without a native plan (any N <= 2048 that is not 2^k or
-// 3 * 2^k): each N-point line DFT is Bluestein's chirp-z form on an M-point
-// line, M the smallest power of two >= 2N - 1.  With kn = (k^2 + n^2 -
-// (k - n)^2) / 2, a DFT of exponent sign S is
-//   X_k = c_k sum_n (x_n c_n) b_(k-n),  c_n = exp(S j pi n^2 / N),
-//   b_m = exp(-S j pi m^2 / N),
-// a linear convolution evaluated as FFT_M -> multiply by FFT_M(b) / M ->
-// inverse FFT_M.  The chirp phases come from the exact integer n^2 mod 2N.
-// FFT_M(b) / M for S = -1 and S = +1 is tabulated once per (device, N,
-// precision) in FP64 on the host.
-template <typename T>
-struct BsArgs {
-    int N;               // line length
-    const cplx<T>* tab;  // [0, M): S = -1, [M, 2M): S = +1
-};
+// Host side of the Bluestein line DFTs (bluestein.hpp): which lengths need
+// them, their padded length and the FFT_M(b) / M tables.
+namespace nslct {
 
 bool native_line(int n) {
     if (n >= 2 && n <= 4096 && (n & (n - 1)) == 0) return true;
@@ -331,8 +322,10 @@ int bluestein_length(int n) {
     return m;
 }
 
+namespace {
 std::mutex g_bs_mu;
 std::vector<std::pair<std::array<int, 4>, void*>> g_bs;  // (device, N, M, fp64) -> table
+}  // namespace
 
 int bs_tables(int N, int M, bool dbl, const void** out) {
     int dev = 0;
@@ -396,116 +389,17 @@ int bs_tables(int N, int M, bool dbl, const void** out) {
     return NSLCT_OK;
 }
 
-// exp(S j 2 pi r / (2N)) * scale, r = n^2 mod 2N (exact), in the working precision.
-__device__ __forceinline__ cplx<float> bs_chirp(int r, int twoN, int S, float scale) {
-    float t = (float)r / (float)twoN;
-    if (t >= 0.5f) t -= 1.f;
-    return {__builtin_amdgcn_cosf(t) * scale, (float)S * __builtin_amdgcn_sinf(t) * scale};
-}
-__device__ __forceinline__ cplx<double> bs_chirp(int r, int twoN, int S, double scale) {
-    double sn, cs;
-    sincospi(2.0 * (double)r / (double)twoN, &sn, &cs);
-    return {cs * scale, (double)S * sn * scale};
-}
+}  // namespace nslct
 
-// One pass on lines of length N through M-point Bluestein line DFTs; the
-// pass structure ([pre] DFT [mid] [DFT], remaps, centring) is that of
-// pass_body, with every sample access restricted to positions < N.
+namespace {
+
+// One Bluestein pass of a single-image launch: tile from the XCD-aware
+// order, image from blockIdx.y.
 template <typename T, int M, bool COL, int LINES>
 __global__ void __launch_bounds__(LinePlan<M>::TPL* LINES) nslct_bs_pass(PassArgs<T> a, BsArgs<T> bs) {
-    constexpr int TPL = LinePlan<M>::TPL;
-    using F = LineFFT<T, M, TPL>;
-    constexpr int E = F::E;
-    constexpr int R0 = F::R0;
-    constexpr int LL = lds_line_elems<M>();
-    __shared__ cplx<T> lds_all[LINES * LL];
-
-    const int N = bs.N, twoN = 2 * N;
-    const int tid = threadIdx.x;
-    const int slot = tid / TPL;
-    const int t = tid % TPL;
+    __shared__ cplx<T> lds_all[LINES * lds_line_elems<M>()];
     const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int line = tile * LINES + slot;
-    const int nl = a.nlines;
-    const bool active = line < nl;
-    cplx<T>* lds = lds_all + slot * LL;
-    const cplx<T>* __restrict__ tab = twiddles<T>();
-    const size_t img_off = (size_t)blockIdx.y * a.img_stride;
-    const cplx<T>* __restrict__ in = a.in + img_off;
-    cplx<T>* __restrict__ out = a.out + img_off;
-
-    cplx<T> w[F::TW];
-    F::preload(w, t, tab);
-    auto pos = [&](int r) { return t + TPL * (r / R0) + (r % R0) * (M / R0); };
-    auto to_store = [&](int p) { const int q = p + N / 2; return q >= N ? q - N : q; };
-    auto addr = [&](int p) { return COL ? (size_t)p * nl + line : (size_t)line * N + p; };
-
-    cplx<T> v[E];
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int p = pos(r);
-        v[r] = (active && p < N) ? in[addr(a.load_remap ? to_store(p) : p)] : cplx<T>{0, 0};
-    }
-
-    const int lc = a.line_centered ? line - nl / 2 : (line >= (nl + 1) / 2 ? line - nl : line);
-    const uint64_t l64 = (uint64_t)(int64_t)lc;
-    auto chirp = [&](const ChirpArg& c, T scale) {
-        const uint64_t A = (COL ? c.c22 : c.c11) * (l64 * l64) + c.c00;
-        const uint64_t Bc = c.c12 * l64;
-        const uint64_t Q = COL ? c.c11 : c.c22;
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int p = pos(r);
-            const int64_t ks = p < (N + 1) / 2 ? p : p - N;
-            const uint64_t k64 = (uint64_t)ks;
-            const uint64_t ph = A + Bc * k64 + Q * (k64 * k64);
-            if (p < N) v[r] = cmul(v[r], turns_cs(ph, scale));
-        }
-    };
-    // N-point DFT of exponent sign S of the positions < N (natural order in
-    // and out, zero beyond N).
-    auto bdft = [&](int S) {
-        const cplx<T>* __restrict__ bt = bs.tab + (S < 0 ? 0 : M);
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int p = pos(r);
-            const int rr = (int)(((long long)p * p) % twoN);
-            v[r] = p < N ? cmul(v[r], bs_chirp(rr, twoN, S, (T)1)) : cplx<T>{0, 0};
-        }
-        F::template dft<-1>(v, lds, t, w, tab);
-#pragma unroll
-        for (int r = 0; r < E; ++r) v[r] = cmul(v[r], bt[pos(r)]);
-        F::template dft<+1>(v, lds, t, w, tab);
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int p = pos(r);
-            const int rr = (int)(((long long)p * p) % twoN);
-            v[r] = p < N ? cmul(v[r], bs_chirp(rr, twoN, S, (T)1)) : cplx<T>{0, 0};
-        }
-    };
-
-    if (a.pre.on) chirp(a.pre, (T)1);
-    const int ndft = a.has_t2 ? 2 : 1;
-#pragma nounroll
-    for (int k = 0; k < ndft; ++k) {
-        bdft(k == 0 ? a.sign1 : a.sign2);
-        if (k == 0 && a.mid_on) {
-            if (a.mid.on) {
-                chirp(a.mid, a.scale);
-            } else {
-#pragma unroll
-                for (int r = 0; r < E; ++r) v[r] = {v[r].re * a.scale, v[r].im * a.scale};
-            }
-        }
-    }
-
-    if (active) {
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int p = pos(r);
-            if (p < N) out[addr(a.store_remap ? to_store(p) : p)] = v[r];
-        }
-    }
+    bs_body<T, M, COL, LINES>(a, bs, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
 }
 
 template <typename T, int M, bool COL>
@@ -633,10 +527,18 @@ int check_ptrs(const void* in, const void* out) {
     return NSLCT_OK;
 }
 
-int run_chain(nslct_plan_t plan, int dir, int count, const void* in, void* out, void* stream) {
+int run_chain(nslct_plan_t plan, int dir, int count, const void* in, void* out, void* stream, bool element_aligned) {
     if (!plan) return fail(NSLCT_E_ARG, "null plan");
     if (count < 0 || count > 65535) return fail(NSLCT_E_ARG, "count must be in [0, 65535]");
-    int rc = check_ptrs(in, out);
+    int rc = NSLCT_OK;
+    if (element_aligned) {
+        const uintptr_t es = plan->d.precision == NSLCT_C128 ? 16 : 8;
+        if (!in || !out) rc = fail(NSLCT_E_ARG, "null image pointer");
+        else if (((uintptr_t)in % es) || ((uintptr_t)out % es))
+            rc = fail(NSLCT_E_ARG, "image pointers must be aligned to a sample");
+    } else {
+        rc = check_ptrs(in, out);
+    }
     if (rc) return rc;
     if (count == 0) return NSLCT_OK;
     rc = ensure_device_ready();

@@ -46,11 +46,12 @@ TPL = {0: {64: 8, 128: 16, 192: 8, 256: 16, 384: 16, 512: 64, 768: 32, 1024: 64}
        1: {64: 16, 128: 8, 192: 16, 256: 32, 384: 32, 512: 32, 768: 64, 1024: 32}}
 
 
-def _plan0(b):
-    """Every group on line plan 0 (the single-image kernels' split of a
-    line), 256 threads per work item, its tuned grid."""
+def _plan0(b, skip=()):
+    """Every native group on line plan 0 (the single-image kernels' split of
+    a line), 256 threads per work item, its tuned grid."""
     for (col, N), sch in b.schedules().items():
-        b.set_group(col, N, 256 // TPL[0][N], sch["mult"], plan=0)
+        if N not in skip:
+            b.set_group(col, N, 256 // TPL[0][N], sch["mult"], plan=0)
 
 
 def _rel(a, b):
@@ -109,10 +110,38 @@ def test_batched_c128(torch, nl):
         assert chain.rel_l2(got[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny), ref) <= 1e-11
 
 
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_bluestein_sizes_in_a_batch(torch, nl, precision):
+    """Sides without a native line plan (Bluestein line DFTs) batch with the
+    native ones: every image against the FP64 oracle, the graph replay
+    against the per-image loop bitwise (same Bluestein code), inverse round
+    trip; the zero-padding sizes 165 + dN of the accuracy sweep in one batch."""
+    sizes = [100, 165, 175, 64, 185, 257, 128, 300]
+    b, oplans = _batch(nl, sizes, seed=51, precision=precision, rect=True)
+    g = synth.complex_normal((b.total,), seed=8)
+    dt = torch.complex64 if precision == "c64" else torch.complex128
+    tol = 1e-5 if precision == "c64" else 1e-11
+    x = torch.from_numpy(g).to(dt).cuda()
+    out = b.forward(x)
+    got = out.cpu().numpy()
+    for o, p, po in zip(b.offsets, b.plans, oplans):
+        ref = chain.forward(po, g[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny))
+        assert chain.rel_l2(got[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny), ref) <= tol, (p.Nx, p.Ny)
+    sch = b.schedules()
+    for N in (100, 165, 175, 185, 257, 300):
+        assert sch[(1, N)]["plan"] == 0
+    _plan0(b, skip=(100, 165, 175, 185, 257, 300))
+    assert torch.equal(b.forward(x), b.run(x, mode=2))
+    back = b.inverse(out).cpu().numpy()
+    assert chain.rel_l2(back, g) <= tol
+
+
 def test_batch_rejects_bad_input(torch, nl):
     M = next(synth.symplectic_candidates(1))
     with pytest.raises(nl.NslctError):
         nl.Batch([nl.Plan(M, 2048, 2048)])
+    with pytest.raises(nl.NslctError):  # native, but not a batched line length
+        nl.Batch([nl.Plan(M, 48, 64)])
     with pytest.raises(nl.NslctError):
         nl.Batch([nl.Plan(M, 64, 64), nl.Plan(M, 64, 64, precision="c128")])
 
