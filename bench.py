@@ -60,8 +60,8 @@ def traffic_from_profile() -> dict:
     return {"rows": int(m.group(1)), "cols": int(m.group(2))}
 
 
-KERNEL_NAMES = {"rows": "nslct_pass<float, 1024, false, 4> (passes 0, 2, 4: row lines)",
-                "cols": "nslct_pass<float, 1024, true, 4> (passes 1, 3: column lines)"}
+KERNEL_NAMES = {"rows": "nslct_pass<float, 1024, false, 4, false, 0> (passes 0, 2, 4: row lines)",
+                "cols": "nslct_pass<float, 1024, true, 4, false, 0> (passes 1, 3: column lines)"}
 
 
 def draw_matrix(seed: int, N: int, d: float, nl):
