@@ -48,8 +48,9 @@
  *   on a power-of-two line of at least 2N - 1 samples (about four times the
  *   arithmetic; its tables are computed on the host and uploaded on the
  *   first transform of that length on a device, so that first call must not
- *   be inside a stream capture).  The ragged batch takes them too; the
- *   backward and split-precision entry points take native lengths only.
+ *   be inside a stream capture).  The ragged batch and the backward sweep
+ *   take them too (not the allocation-free backward entry point); the
+ *   split-precision paths take sides 256 and 4096 only.
  */
 #ifndef NSLCT_H
 #define NSLCT_H
@@ -276,7 +277,9 @@ void nslct_batch_destroy(nslct_batch_t batch);
  * array sums[15] (caller-zeroed, accumulated over images; must not be read
  * before the stream reaches this call) the sums of Im(conj(adjoint) signal)
  * weighted by x^2, x y, y^2.  On return grad_x = L^H grad_out = dLoss/dx.
- * Sides 8..1024 (2^k) or 48, 96, 192, 384, 768; work, grad_x distinct buffers. */
+ * Sides 8..1024 (2^k), 48, 96, 192, 384, 768, or any length up to 2048
+ * without a native plan (Bluestein lines; their tables are made on the first
+ * call with that length on a device); work, grad_x distinct buffers. */
 int nslct_backward(nslct_plan_t plan, int count, const void* G, const void* grad_out, void* work, void* grad_x,
                    double* sums, void* stream);
 
@@ -307,8 +310,10 @@ int nslct_backward_theta(nslct_plan_t plan, int count, const void* G, const void
  * bytes per device (held from the library's first use of that device until
  * the process ends); images are swept in chunks of up to 16 MiB, so any
  * count is accepted, and a single image above 16 MiB is NSLCT_E_SIZE
- * (unreachable with the backward sizes, whose largest image is 1024 x 1024
- * complex128 = 16 MiB).  The sums are cleared by a kernel at the start of
+ * (unreachable with its sizes, whose largest image is 1024 x 1024
+ * complex128 = 16 MiB).  Native sides only: a side without a native line
+ * plan is NSLCT_E_SIZE (its Bluestein table would be allocated).  The sums
+ * are cleared by a kernel at the start of
  * every call.  Every call on one device shares that device's array: calls
  * that overlap in time on one device (several host threads, or streams
  * that run concurrently) race and give wrong results. */

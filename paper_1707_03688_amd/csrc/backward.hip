@@ -10,6 +10,7 @@
 
 #include "internal.hpp"
 #include "pass_kernels.hpp"
+#include "bluestein.hpp"
 
 using namespace nslct;
 
@@ -26,7 +27,7 @@ __global__ void __launch_bounds__((PlanVariant<N, V>::TPL * LINES)) nslct_pair_p
 
 #define NSLCT_PAIR_SIZES(X) X(8) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
-bool pair_size_ok(int n) {
+bool pair_native_size(int n) {
     switch (n) {
 #define NSLCT_PAIR_OK(v) case v:
         NSLCT_PAIR_SIZES(NSLCT_PAIR_OK)
@@ -34,6 +35,44 @@ bool pair_size_ok(int n) {
         return true;
         default:
             return false;
+    }
+}
+// Sides of the backward sweep: the native ones above and every length up to
+// 2048 without a native plan (Bluestein line DFTs).
+bool pair_size_ok(int n) { return pair_native_size(n) || (n >= 2 && n <= 2048 && !native_line(n)); }
+
+// Paired Bluestein pass (lines without a native plan).
+template <typename T, int M, bool COL, int LINES>
+__global__ void __launch_bounds__(LinePlan<M>::TPL* LINES) nslct_pair_bs_pass(PassArgs<T> a, BsArgs<T> bs) {
+    __shared__ cplx<T> lds_all[LINES * lds_line_elems<M>()];
+    const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    bs_body<T, M, COL, LINES, 2>(a, bs, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
+}
+template <typename T, int M, bool COL>
+hipError_t launch_pair_bs_m(const PassArgs<T>& a, const BsArgs<T>& bs, int count, hipStream_t s) {
+    constexpr int L = COL ? col_lines<T, M>() : row_lines<T, M>();
+    hipLaunchKernelGGL((nslct_pair_bs_pass<T, M, COL, L>), dim3((a.nlines + L - 1) / L, count),
+                       dim3(LinePlan<M>::TPL * L), 0, s, a, bs);
+    return hipGetLastError();
+}
+template <typename T, bool COL>
+hipError_t launch_pair_bs(int N, const PassArgs<T>& a, int count, hipStream_t s) {
+    const int M = bluestein_length(N);
+    const void* tabp = nullptr;
+    if (bs_tables(N, M, sizeof(T) == 8, &tabp) != NSLCT_OK) return hipErrorInvalidValue;
+    const BsArgs<T> bs{N, (const cplx<T>*)tabp};
+    switch (M) {
+        case 8: return launch_pair_bs_m<T, 8, COL>(a, bs, count, s);
+        case 16: return launch_pair_bs_m<T, 16, COL>(a, bs, count, s);
+        case 32: return launch_pair_bs_m<T, 32, COL>(a, bs, count, s);
+        case 64: return launch_pair_bs_m<T, 64, COL>(a, bs, count, s);
+        case 128: return launch_pair_bs_m<T, 128, COL>(a, bs, count, s);
+        case 256: return launch_pair_bs_m<T, 256, COL>(a, bs, count, s);
+        case 512: return launch_pair_bs_m<T, 512, COL>(a, bs, count, s);
+        case 1024: return launch_pair_bs_m<T, 1024, COL>(a, bs, count, s);
+        case 2048: return launch_pair_bs_m<T, 2048, COL>(a, bs, count, s);
+        case 4096: return launch_pair_bs_m<T, 4096, COL>(a, bs, count, s);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -71,8 +110,11 @@ hipError_t run_backward_t(const PlanData& d, int count, int plan_count, const vo
         a.out2 = (cplx<T>*)gx;
         a.acc = sums + 3 * pass;
         const bool col = (pass == 1 || pass == 3);
-        const hipError_t e = col ? launch_pair_n<T, true>(d.Nx, a, count, plan_count, s)
-                                 : launch_pair_n<T, false>(d.Ny, a, count, plan_count, s);
+        const int N = col ? d.Nx : d.Ny;
+        const hipError_t e = !pair_native_size(N) ? (col ? launch_pair_bs<T, true>(N, a, count, s)
+                                                         : launch_pair_bs<T, false>(N, a, count, s))
+                             : col ? launch_pair_n<T, true>(N, a, count, plan_count, s)
+                                   : launch_pair_n<T, false>(N, a, count, plan_count, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -94,9 +136,21 @@ int check_backward(nslct_plan_t plan, int count, const void* G, const void* grad
     if (d.precision != NSLCT_C64 && d.precision != NSLCT_C128)
         return fail(NSLCT_E_UNSUPPORTED, "backward runs complex64 or complex128 plans");
     if (!pair_size_ok(d.Nx) || !pair_size_ok(d.Ny))
-        return fail(NSLCT_E_SIZE, "backward sides must be 8..1024 (2^k) or 48, 96, 192, 384, 768");
+        return fail(NSLCT_E_SIZE, "backward sides must be 8..1024 (2^k), 48, 96, 192, 384, 768, or a length up to 2048 without a native plan");
     if (d.st.type == 7) return fail(NSLCT_E_UNSUPPORTED, "the backward sweep runs five-slot chains (not type 7)");
     if (grad_x == G) return fail(NSLCT_E_ARG, "grad_x must be distinct from G");
+    return NSLCT_OK;
+}
+
+// Bluestein tables of the plan's non-native axes on the current device
+// (made on first use; host work and a device allocation).
+int pair_tables(const PlanData& d) {
+    for (int n : {d.Nx, d.Ny}) {
+        if (pair_native_size(n)) continue;
+        const void* tabp = nullptr;
+        const int rc = bs_tables(n, bluestein_length(n), d.precision == NSLCT_C128, &tabp);
+        if (rc) return rc;
+    }
     return NSLCT_OK;
 }
 
@@ -186,11 +240,12 @@ int nslct_backward(nslct_plan_t plan, int count, const void* G, const void* grad
     if (d.precision != NSLCT_C64 && d.precision != NSLCT_C128)
         return fail(NSLCT_E_UNSUPPORTED, "backward runs complex64 or complex128 plans");
     if (!pair_size_ok(d.Nx) || !pair_size_ok(d.Ny))
-        return fail(NSLCT_E_SIZE, "backward sides must be 8..1024 (2^k) or 48, 96, 192, 384, 768");
+        return fail(NSLCT_E_SIZE, "backward sides must be 8..1024 (2^k), 48, 96, 192, 384, 768, or a length up to 2048 without a native plan");
     if (d.st.type == 7) return fail(NSLCT_E_UNSUPPORTED, "the backward sweep runs five-slot chains (not type 7)");
     if (work == grad_x || work == G || work == grad_out || grad_x == G)
         return fail(NSLCT_E_ARG, "work and grad_x must be distinct from each other and from G");
     rc = ensure_device_ready();
+    if (!rc) rc = pair_tables(d);
     if (rc) return rc;
     const hipError_t e = d.precision == NSLCT_C128
                              ? run_backward_t<double>(d, count, count, G, grad_out, work, grad_x, sums, (hipStream_t)stream)
@@ -209,6 +264,7 @@ int nslct_backward_theta(nslct_plan_t plan, int count, const void* G, const void
         if (rc) return rc;
     }
     rc = ensure_device_ready();
+    if (!rc) rc = pair_tables(d);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     const size_t es = d.precision == NSLCT_C128 ? 16 : 8;
@@ -238,6 +294,8 @@ int nslct_backward_theta_noalloc(nslct_plan_t plan, int count, const void* G, co
     const size_t img = (size_t)d.Nx * d.Ny * es;
     if (img > kNoallocWorkBytes)
         return fail(NSLCT_E_SIZE, "an image is larger than the 16 MiB scratch work region");
+    if (!pair_native_size(d.Nx) || !pair_native_size(d.Ny))
+        return fail(NSLCT_E_SIZE, "the allocation-free backward takes native lengths (Bluestein tables are allocated)");
     const double* jac = nullptr;
     if (grad_theta) {
         rc = plan_jac(plan, &jac);

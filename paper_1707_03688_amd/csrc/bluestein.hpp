@@ -37,8 +37,10 @@ __device__ __forceinline__ cplx<double> bs_chirp(int r, int twoN, int S, double 
 // One pass on lines of length N through M-point Bluestein line DFTs, for
 // the line tile `tile` of the image at sample offset img_off; the pass
 // structure ([pre] DFT [mid] [DFT], remaps, centring) is that of pass_body,
-// with every sample access restricted to positions < N.
-template <typename T, int M, bool COL, int LINES>
+// with every sample access restricted to positions < N.  NS = 2: the
+// backward sweep's two signals (a.in / a.out and a.in2 / a.out2) through the
+// same steps, with the gradient sums of pass_body at the chirp point.
+template <typename T, int M, bool COL, int LINES, int NS = 1>
 __device__ __forceinline__ void bs_body(const PassArgs<T>& a, const BsArgs<T>& bs, int tile, size_t img_off,
                                         cplx<T>* lds_all) {
     constexpr int TPL = LinePlan<M>::TPL;
@@ -56,21 +58,25 @@ __device__ __forceinline__ void bs_body(const PassArgs<T>& a, const BsArgs<T>& b
     const bool active = line < nl;
     cplx<T>* lds = lds_all + slot * LL;
     const cplx<T>* __restrict__ tab = twiddles<T>();
-    const cplx<T>* __restrict__ in = a.in + img_off;
-    cplx<T>* __restrict__ out = a.out + img_off;
+    const cplx<T>* ins[2] = {a.in + img_off, NS > 1 ? a.in2 + img_off : nullptr};
+    cplx<T>* outs[2] = {a.out + img_off, NS > 1 ? a.out2 + img_off : nullptr};
 
     cplx<T> w[F::TW];
     F::preload(w, t, tab);
     auto pos = [&](int r) { return t + TPL * (r / R0) + (r % R0) * (M / R0); };
     auto to_store = [&](int p) { const int q = p + N / 2; return q >= N ? q - N : q; };
     auto addr = [&](int p) { return COL ? (size_t)p * nl + line : (size_t)line * N + p; };
+    // Signed index along the line of FFT-order position p (as the chirps use it).
+    auto signed_k = [&](int p) { return p < (N + 1) / 2 ? p : p - N; };
 
-    cplx<T> v[E];
+    cplx<T> v[NS][E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-        const int p = pos(r);
-        v[r] = (active && p < N) ? in[addr(a.load_remap ? to_store(p) : p)] : cplx<T>{0, 0};
-    }
+    for (int sg = 0; sg < NS; ++sg)
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const int p = pos(r);
+            v[sg][r] = (active && p < N) ? ins[sg][addr(a.load_remap ? to_store(p) : p)] : cplx<T>{0, 0};
+        }
 
     const int lc = a.line_centered ? line - nl / 2 : (line >= (nl + 1) / 2 ? line - nl : line);
     const uint64_t l64 = (uint64_t)(int64_t)lc;
@@ -81,55 +87,101 @@ __device__ __forceinline__ void bs_body(const PassArgs<T>& a, const BsArgs<T>& b
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int p = pos(r);
-            const int64_t ks = p < (N + 1) / 2 ? p : p - N;
-            const uint64_t k64 = (uint64_t)ks;
+            const uint64_t k64 = (uint64_t)(int64_t)signed_k(p);
             const uint64_t ph = A + Bc * k64 + Q * (k64 * k64);
-            if (p < N) v[r] = cmul(v[r], turns_cs(ph, scale));
+            const cplx<T> f = turns_cs(ph, scale);
+#pragma unroll
+            for (int sg = 0; sg < NS; ++sg)
+                if (p < N) v[sg][r] = cmul(v[sg][r], f);
         }
     };
+    auto scale_all = [&](T sc) {
+#pragma unroll
+        for (int sg = 0; sg < NS; ++sg)
+#pragma unroll
+            for (int r = 0; r < E; ++r) v[sg][r] = {v[sg][r].re * sc, v[sg][r].im * sc};
+    };
     // N-point DFT of exponent sign S of the positions < N (natural order in
-    // and out, zero beyond N).
-    auto bdft = [&](int S) {
+    // and out, zero beyond N), of signal sg.
+    auto bdft = [&](int S, int sg) {
         const cplx<T>* __restrict__ bt = bs.tab + (S < 0 ? 0 : M);
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int p = pos(r);
             const int rr = (int)(((long long)p * p) % twoN);
-            v[r] = p < N ? cmul(v[r], bs_chirp(rr, twoN, S, (T)1)) : cplx<T>{0, 0};
+            v[sg][r] = p < N ? cmul(v[sg][r], bs_chirp(rr, twoN, S, (T)1)) : cplx<T>{0, 0};
         }
-        F::template dft<-1>(v, lds, t, w, tab);
+        F::template dft<-1>(v[sg], lds, t, w, tab);
 #pragma unroll
-        for (int r = 0; r < E; ++r) v[r] = cmul(v[r], bt[pos(r)]);
-        F::template dft<+1>(v, lds, t, w, tab);
+        for (int r = 0; r < E; ++r) v[sg][r] = cmul(v[sg][r], bt[pos(r)]);
+        F::template dft<+1>(v[sg], lds, t, w, tab);
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             const int p = pos(r);
             const int rr = (int)(((long long)p * p) % twoN);
-            v[r] = p < N ? cmul(v[r], bs_chirp(rr, twoN, S, (T)1)) : cplx<T>{0, 0};
+            v[sg][r] = p < N ? cmul(v[sg][r], bs_chirp(rr, twoN, S, (T)1)) : cplx<T>{0, 0};
+        }
+    };
+    // Backward sweep: at the chirp point, sum Im(conj(adjoint) * signal)
+    // weighted by x^2, x y, y^2 (signed sample indices) into a.acc[0..2].
+    auto gradient_sums = [&]() {
+        if constexpr (NS == 2) {
+            double sxx = 0, sxy = 0, syy = 0;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int p = pos(r);
+                if (p >= N) continue;
+                const double e = (double)signed_k(p);
+                const double xi = COL ? e : (double)lc;
+                const double yi = COL ? (double)lc : e;
+                const double im = (double)v[1][r].re * (double)v[0][r].im - (double)v[1][r].im * (double)v[0][r].re;
+                sxx += xi * xi * im;
+                sxy += xi * yi * im;
+                syy += yi * yi * im;
+            }
+            block_sum3(sxx, sxy, syy, a.acc);
         }
     };
 
-    if (a.pre.on) chirp(a.pre, (T)1);
-    const int ndft = a.has_t2 ? 2 : 1;
+    if constexpr (NS == 1) {
+        if (a.pre.on) chirp(a.pre, (T)1);
+        const int ndft = a.has_t2 ? 2 : 1;
 #pragma nounroll
-    for (int k = 0; k < ndft; ++k) {
-        bdft(k == 0 ? a.sign1 : a.sign2);
-        if (k == 0 && a.mid_on) {
-            if (a.mid.on) {
-                chirp(a.mid, a.scale);
-            } else {
-#pragma unroll
-                for (int r = 0; r < E; ++r) v[r] = {v[r].re * a.scale, v[r].im * a.scale};
+        for (int k = 0; k < ndft; ++k) {
+            bdft(k == 0 ? a.sign1 : a.sign2, 0);
+            if (k == 0 && a.mid_on) {
+                if (a.mid.on)
+                    chirp(a.mid, a.scale);
+                else
+                    scale_all(a.scale);
             }
+        }
+    } else {
+        if (!a.mid_on) gradient_sums();
+        if (a.pre.on) chirp(a.pre, (T)1);
+#pragma unroll
+        for (int sg = 0; sg < NS; ++sg) bdft(a.sign1, sg);
+        if (a.mid_on) {
+            gradient_sums();
+            if (a.mid.on)
+                chirp(a.mid, a.scale);
+            else
+                scale_all(a.scale);
+        }
+        if (a.has_t2) {
+#pragma unroll
+            for (int sg = 0; sg < NS; ++sg) bdft(a.sign2, sg);
         }
     }
 
     if (active) {
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const int p = pos(r);
-            if (p < N) out[addr(a.store_remap ? to_store(p) : p)] = v[r];
-        }
+        for (int sg = 0; sg < NS; ++sg)
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const int p = pos(r);
+                if (p < N) outs[sg][addr(a.store_remap ? to_store(p) : p)] = v[sg][r];
+            }
     }
 }
 

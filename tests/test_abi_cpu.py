@@ -302,6 +302,14 @@ def test_lie_plans_and_theta_gradient_errors(nl):
     o = nl.lib.opts()
     o.det_min = 0.0
     assert _cplan(nl, M0, opts=o) == -1
+    # Backward sides: Bluestein lengths are accepted by the allocating entry
+    # points but refused, before any device work, by the allocation-free one
+    # (its tables would be allocated); a native length outside the backward
+    # set is refused by both.
+    pb = nl.Plan.lie(M0, th, 30, 45, 0.5, 0.6, symplectic_tol=1e-8)
+    assert nl.lib.nslct_backward_theta_noalloc(pb._h, 1, fake, fake, ctypes.c_void_p(2 << 20), gt, None) == -4
+    pn = nl.Plan.lie(M0, th, 2048, 8, 0.5, 0.6, symplectic_tol=1e-8)
+    assert nl.lib.nslct_backward_theta(pn._h, 1, fake, fake, ctypes.c_void_p(2 << 20), gt, None) == -4
 
 
 def test_box_check_agrees_with_oracle_predicate(nl):
