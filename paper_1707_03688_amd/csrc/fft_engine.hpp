@@ -319,9 +319,10 @@ struct LinePlan<768> {
 };
 
 // Alternative line plans (V = 1) that the ragged batch's schedule tuner
-// times against LinePlan<N> (V = 0): another split of the line over
-// threads and radices, the first and last radix equal and every radix
-// dividing the per-thread sample count, lines still inside one wavefront.
+// times against LinePlan<N> (V = 0) and that the single-image passes take
+// where they measured faster: another split of the line over threads and
+// radices, the first and last radix equal and every radix dividing the
+// per-thread sample count (lines inside one wavefront up to 1024).
 template <int N, int V>
 struct PlanVariant : LinePlan<N> {
     static constexpr bool exists = V == 0;
@@ -341,6 +342,7 @@ NSLCT_PLAN_VARIANT(384, 32, 4, 6, 4, 4)
 NSLCT_PLAN_VARIANT(512, 32, 16, 2, 16)
 NSLCT_PLAN_VARIANT(768, 64, 4, 12, 4, 4)
 NSLCT_PLAN_VARIANT(1024, 32, 16, 4, 16)
+NSLCT_PLAN_VARIANT(4096, 128, 16, 16, 16)
 #undef NSLCT_PLAN_VARIANT
 
 // LDS index of line position p (one padding element every 16).

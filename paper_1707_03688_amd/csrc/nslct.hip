@@ -98,7 +98,11 @@ hipError_t launch_tv(const PassArgs<T>& a, int count, hipStream_t s) {
 template <typename T, int N, bool COL, bool X3 = false>
 hipError_t launch_t(const PassArgs<T>& a, int count, hipStream_t s) {
     if constexpr (sizeof(T) == 4 && PlanVariant<N, 1>::exists) {
-        if (alt_plan(N, (long long)a.nlines * count)) return launch_tv<T, N, COL, X3, 1>(a, count, s);
+        // 4096-long rows with one line DFT (the first and last pass of a
+        // chain) run faster on 128 threads; the two-DFT middle pass and the
+        // column tiles keep the 256-thread plan.
+        const bool alt = N == 4096 ? (!COL && !X3 && !a.has_t2) : alt_plan(N, (long long)a.nlines * count);
+        if (alt) return launch_tv<T, N, COL, X3, 1>(a, count, s);
     }
     return launch_tv<T, N, COL, X3, 0>(a, count, s);
 }
