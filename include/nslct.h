@@ -197,6 +197,13 @@ int nslct_inverse_many(nslct_plan_t plan, int count, const void* in, void* out, 
 int nslct_launch_pass(nslct_plan_t plan, int direction, int pass, int count,
                       const void* in, void* out, void* stream);
 
+/* Makes, on the current device, every device table the plan's transforms
+ * use (the library's twiddle tables, and the Bluestein tables of a side
+ * without a native line plan), which the first transform would otherwise
+ * make.  After it, transforms of the plan on this device allocate nothing
+ * and may be captured into a HIP graph.  Synchronous; idempotent. */
+int nslct_plan_prepare(nslct_plan_t plan);
+
 /* Number of passes of the single-image path of `plan`: 3 for the reduced
  * chains (types 3-5) in complex64 / complex128 at native lengths (2^k,
  * 3 * 2^k), else 5.  Host only. */

@@ -118,6 +118,12 @@ class Plan:
                 "dx": st.dx, "dy": st.dy, "dwx": st.dwx, "dwy": st.dwy, "phase_q": st.phase_q,
                 "Nx": getattr(self, "Nx", None), "Ny": getattr(self, "Ny", None)}
 
+    def prepare(self):
+        """Device tables of the plan on the current device (``nslct_plan_prepare``):
+        afterwards its transforms allocate nothing and can be graph-captured."""
+        check(lib.nslct_plan_prepare(self._h))
+        return self
+
     def passes(self) -> int:
         """Passes of the single-image path (3 for the reduced chains, else 5)."""
         n = ctypes.c_int()

@@ -68,6 +68,7 @@ SIGNATURES = {
     "nslct_inverse_many": (I, [P, I, P, P, P]),
     "nslct_launch_pass": (I, [P, I, I, I, P, P, P]),
     "nslct_plan_passes": (I, [P, ctypes.POINTER(I)]),
+    "nslct_plan_prepare": (I, [P]),
     "nslct_device_copy": (I, [P, P, ctypes.c_size_t, P]),
     "nslct_batch_create": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P)]),
     "nslct_batch_info": (I, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(I), ctypes.POINTER(D)]),

@@ -686,6 +686,13 @@ int nslct_launch_pass(nslct_plan_t plan, int direction, int pass, int count, con
     return NSLCT_OK;
 }
 
+int nslct_plan_prepare(nslct_plan_t plan) {
+    if (!plan) return fail(NSLCT_E_ARG, "null plan");
+    int rc = ensure_device_ready();
+    if (!rc) rc = prepare_plan_tables(plan->d);
+    return rc;
+}
+
 int nslct_plan_passes(nslct_plan_t plan, int* npasses) {
     if (!plan || !npasses) return fail(NSLCT_E_ARG, "null argument");
     *npasses = plan_passes(plan->d);

@@ -108,3 +108,33 @@ def test_printed_additivity_g2_at_165(torch, nl):
     two = _gpu_forward(nl, torch, M4, _gpu_forward(nl, torch, M2, g, d), d)
     one = _gpu_forward(nl, torch, M4 @ M2, g, d)
     assert abs(chain.rel_l2(one, two) ** 2 - pv["nmse_add_ha_g2"]) <= 0.002
+
+
+@pytest.mark.parametrize("shape", [(100, 75), (128, 64)])
+def test_prepared_plan_captures_into_a_graph(torch, nl, shape):
+    """After nslct_plan_prepare a transform allocates nothing, so a
+    Bluestein-length (and a native) forward + inverse captures into a HIP
+    graph; replays with unrelated eager work between them give the eager
+    bits every time."""
+    Nx, Ny = shape
+    M = next(synth.symplectic_candidates(Nx + Ny))
+    d = math.sqrt(2 * math.pi / max(Nx, Ny))
+    plan = nl.Plan(M, Nx, Ny, d, d).prepare()
+    x = torch.from_numpy(synth.complex_normal((2, Nx, Ny), seed=Nx)).to(torch.complex64).cuda()
+    ref = plan.forward(x)
+    ref_back = plan.inverse(ref)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.forward(x, out=y)
+        plan.inverse(y, out=z)
+    for k in range(3):
+        y.zero_()
+        z.zero_()
+        g.replay()
+        junk = torch.randn(1 << 18, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref) and torch.equal(z, ref_back), k
+        del junk
