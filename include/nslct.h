@@ -265,7 +265,12 @@ int nslct_batch_set_grid(nslct_batch_t batch, int mult);
 /* Forward / inverse of every image of the batch: the five passes, each one
  * persistent launch per line length over all images of that length (the
  * launches of one pass run concurrently), captured once per (in, out) pair
- * into a HIP graph that is then replayed on `stream`.  in == out allowed. */
+ * into a HIP graph that is then replayed on `stream`.  When the row and
+ * column line lengths pair up (the images whose rows have length a all have
+ * columns of length b, and no other image has either; square images
+ * always), each pair's five launches form an independent sequence on its
+ * own fork stream, joined once at the end, instead of joining every pass.
+ * in == out allowed. */
 int nslct_forward_batched(nslct_batch_t batch, const void* in, void* out, void* stream);
 int nslct_inverse_batched(nslct_batch_t batch, const void* in, void* out, void* stream);
 

@@ -314,6 +314,10 @@ struct nslct_batch_s {
         double us;    // measured time of one launch of this group while tuning
     };
     std::vector<Group> groups[2];
+    // chain_col[k]: the column group holding exactly the images of row group
+    // k, when every row group has one (then each (row group, column group)
+    // pair is a set of chains that no other group touches); else empty.
+    std::vector<int> chain_col;
     int mult = 0;  // grid override of nslct_batch_set_grid (-1: per-group tuned grids)
     int cus = 256;  // compute units of the device
     double tuned_us = 0.0;
@@ -365,6 +369,24 @@ hipError_t launch_group_pass(const nslct_batch_s& b, int col, const nslct_batch_
 
 template <typename T>
 hipError_t run_batched_t(const nslct_batch_s& b, int dir, const void* in, void* out, hipStream_t s) {
+    const size_t nch = b.chain_col.size();
+    if (nch > 1 && b.side.size() >= nch) {
+        // Independent image sets: each runs its five passes on its own fork
+        // stream, joined once at the end, so a set that finishes a pass
+        // early goes on to the next instead of waiting for the others.
+        hipError_t e = hipEventRecord(b.ev[0], s);
+        for (size_t k = 0; k < nch && e == hipSuccess; ++k) e = hipStreamWaitEvent(b.side[k], b.ev[0], 0);
+        for (size_t k = 0; k < nch && e == hipSuccess; ++k) {
+            for (int pass = 0; pass < 5 && e == hipSuccess; ++pass) {
+                const int col = (pass == 1 || pass == 3) ? 1 : 0;
+                const auto& g = col ? b.groups[1][b.chain_col[k]] : b.groups[0][k];
+                e = launch_group_pass<T>(b, col, g, dir, pass, pass == 0 ? in : out, out, b.side[k]);
+            }
+            if (e == hipSuccess) e = hipEventRecord(b.ev[1 + k], b.side[k]);
+        }
+        for (size_t k = 0; k < nch && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, b.ev[1 + k], 0);
+        return e;
+    }
     for (int pass = 0; pass < 5; ++pass) {
         const int col = (pass == 1 || pass == 3) ? 1 : 0;
         const auto& gs = b.groups[col];
@@ -652,6 +674,22 @@ int nslct_batch_create(const nslct_plan_t* plans, int count, nslct_batch_t* out)
             e = set_group_width(*b, col, b->groups[col].back(), b->groups[col].back().width, 0);
             if (e != hipSuccess) return batch_fail(b, e, "work list upload");
         }
+    }
+    {  // Pair row and column groups that hold the same images (chain_col).
+        auto index_of = [&](int col, int N) {
+            for (size_t k = 0; k < b->groups[col].size(); ++k)
+                if (b->groups[col][k].N == N) return (int)k;
+            return -1;
+        };
+        std::vector<int> pc(b->groups[0].size(), -1), pr(b->groups[1].size(), -1);
+        bool paired = b->groups[0].size() == b->groups[1].size();
+        for (int i = 0; i < count && paired; ++i) {
+            const int r = index_of(0, b->plans[i].d.Ny), c = index_of(1, b->plans[i].d.Nx);
+            if ((pc[r] >= 0 && pc[r] != c) || (pr[c] >= 0 && pr[c] != r)) paired = false;
+            pc[r] = c;
+            pr[c] = r;
+        }
+        if (paired) b->chain_col = pc;
     }
     e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return batch_fail(b, e, "hipStreamCreate");

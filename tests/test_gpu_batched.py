@@ -82,6 +82,37 @@ def test_batched_matches_loop_bitwise_and_oracle(torch, nl, rect):
     assert chain.rel_l2(back, g) <= 1e-5
 
 
+def test_paired_rectangular_batch(torch, nl):
+    """Rectangular images whose row and column line lengths pair up (every
+    image with Ny = 256 has Nx = 512, and so on; a Bluestein length among
+    them): the batch runs each pair's passes as one independent sequence.
+    Against the oracle (every image), the per-image loop (to rounding), graph
+    and plain launches bitwise, and the inverse."""
+    shapes = [(512, 256), (128, 384), (512, 256), (64, 64), (128, 384), (768, 100), (512, 256)]
+    cands = synth.symplectic_candidates(34)
+    plans, oplans = [], []
+    for Nx, Ny in shapes:
+        d = (2 * np.pi / max(Nx, Ny)) ** 0.5
+        po = oplan.plan(next(cands), Nx, Ny, d, d)
+        plans.append(nl.Plan.from_stages(po.typ, po.mats, Nx, Ny, d, d, "c64"))
+        oplans.append(po)
+    b = nl.Batch(plans)
+    g = synth.complex_normal((b.total,), seed=6)
+    x = torch.from_numpy(g).to(torch.complex64).cuda()
+    out_graph = b.forward(x)
+    out_plain = b.run(x, mode=1)
+    out_loop = b.run(x, mode=2)
+    torch.cuda.synchronize()
+    assert torch.equal(out_graph, out_plain)
+    assert _rel(out_graph, out_loop) <= 1e-6
+    got = out_graph.cpu().numpy()
+    for o, p, po in zip(b.offsets, b.plans, oplans):
+        ref = chain.forward(po, g[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny))
+        assert chain.rel_l2(got[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny), ref) <= 1e-5
+    back = b.inverse(out_graph).cpu().numpy()
+    assert chain.rel_l2(back, g) <= 1e-5
+
+
 def test_graph_replays_are_stable(torch, nl):
     """Repeated graph replays with unrelated eager work between them all equal
     the eager (non-graph) result; in-place replays too."""
