@@ -137,8 +137,10 @@ __device__ __forceinline__ int store_to_fft(int p) {
 // longer than a wavefront, their loads) are staged through LDS so that the
 // global accesses cover LINES consecutive samples of each row (coalesced),
 // while each line's FFT work stays with the TPL threads that own it.
+// `img`, when given, replaces a.in and a.out (an image held in LDS).
 template <typename T, int N, bool COL, int LINES, int NS = 1, bool X3 = false, typename PP = LinePlan<N>>
-__device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t img_off, cplx<T>* lds_all) {
+__device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t img_off, cplx<T>* lds_all,
+                                          cplx<T>* img = nullptr) {
     constexpr int TPL = PP::TPL;
     using F = LineFFT<T, N, TPL, typename PP::L>;
     constexpr int E = F::E;
@@ -154,8 +156,8 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
     const bool active = line < nl;
     cplx<T>* lds = lds_all + slot * LL;
     const cplx<T>* __restrict__ tab = twiddles<T>();
-    const cplx<T>* ins[2] = {a.in + img_off, NS > 1 ? a.in2 + img_off : nullptr};
-    cplx<T>* outs[2] = {a.out + img_off, NS > 1 ? a.out2 + img_off : nullptr};
+    const cplx<T>* ins[2] = {img ? img : a.in + img_off, NS > 1 ? a.in2 + img_off : nullptr};
+    cplx<T>* outs[2] = {img ? img : a.out + img_off, NS > 1 ? a.out2 + img_off : nullptr};
 
     cplx<T> w[F::TW];
     F::preload(w, t, tab);
