@@ -184,7 +184,9 @@ int nslct_inverse(nslct_plan_t plan, const void* in, void* out, void* stream);
  * complex64 passes over lines of length 64, 192, 256, 384, 512, 768 or 1024
  * the split of a line over threads is chosen by the number of lines in
  * flight (lines of the pass times count), so one image's result may differ
- * in its last bits with `count` (every result within the complex64 bar).
+ * in its last bits with `count` (every result within the complex64 bar);
+ * complex128 passes over lines of length 64, 192, 256, 384 or 768 always
+ * take the alternative split.
  * Square 32 x 32 images, and 64 x 64 images from 32 (complex64) or 128
  * (complex128) per call, run the whole chain in one launch with each image
  * held in LDS (one workgroup per image, the passes' own line split). */

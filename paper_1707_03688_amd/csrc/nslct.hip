@@ -104,6 +104,7 @@ hipError_t launch_t(const PassArgs<T>& a, int count, hipStream_t s) {
         const bool alt = N == 4096 ? (!COL && !X3 && !a.has_t2) : alt_plan(N, (long long)a.nlines * count);
         if (alt) return launch_tv<T, N, COL, X3, 1>(a, count, s);
     }
+    if constexpr (sizeof(T) == 8 && alt_plan_c128(N)) return launch_tv<T, N, COL, X3, 1>(a, count, s);
     return launch_tv<T, N, COL, X3, 0>(a, count, s);
 }
 

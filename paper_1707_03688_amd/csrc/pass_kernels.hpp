@@ -416,9 +416,10 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
 // measured on gfx950 (complex64, square images, all counts alike), it is
 // faster for 192 always, for 256, 384 and 768 when few lines are in flight,
 // and for 64, 512 and 1024 when many are; `lines` = lines of the pass times
-// images.  (Complex128 and the other lengths keep LinePlan<N>.)  The
-// backward sweep's paired passes follow the same rule except at 1024, where
-// their two signals make the alternative slower at every count measured.
+// images.  (Complex128: alt_plan_c128; the other lengths keep LinePlan<N>.)
+// The backward sweep's paired passes follow the same rule except at 1024,
+// where their two signals make the alternative slower at every count
+// measured.
 inline bool alt_plan(int N, long long lines) {
     switch (N) {
         case 64: return lines >= 1024;
@@ -431,6 +432,13 @@ inline bool alt_plan(int N, long long lines) {
         default: return false;
     }
 }
+
+// Complex128 single-image passes: the alternative split is faster at every
+// image count measured (1 to 64) for 64, 192, 256, 384 and 768 (FP64 line
+// DFTs gain more from the shorter per-thread chains: one image of 192^2
+// 69.5 -> 40.5 us, 256^2 42.7 -> 30.0, 768^2 99.5 -> 68.0) and slower for
+// 128 (29.2 -> 46.0 us) and 512.
+constexpr bool alt_plan_c128(int N) { return N == 64 || N == 192 || N == 256 || N == 384 || N == 768; }
 
 template <typename P>
 constexpr int row_lines_of() {

@@ -162,6 +162,10 @@ def test_bluestein_sizes_in_a_batch(torch, nl, precision):
     for N in (100, 165, 175, 185, 257, 300):
         assert sch[(1, N)]["plan"] == 0
     _plan0(b, skip=(100, 165, 175, 185, 257, 300))
+    if precision == "c128":  # the single-image passes split 64-long complex128 lines the other way
+        for (col, N), sch in b.schedules().items():
+            if N == 64:
+                b.set_group(col, N, 256 // TPL[1][N], sch["mult"], plan=1)
     assert torch.equal(b.forward(x), b.run(x, mode=2))
     back = b.inverse(out).cpu().numpy()
     assert chain.rel_l2(back, g) <= tol

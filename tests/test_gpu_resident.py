@@ -1,7 +1,9 @@
 """GPU tests of the single-launch chain for small square images held in LDS
 (32 x 32 at every image count, 64 x 64 from 32 complex64 / 128 complex128
 images per call): every image equals the pass-by-pass launches of the same
-plan bit for bit (both run line plan 0), selected images match the FP64
+plan bit for bit where both run line plan 0 (complex128 passes over 64-long
+lines take the alternative split, so there the two agree to rounding,
+relative L2 <= 1e-13), selected images match the FP64
 oracle element by element (relative L2: complex64 <= 1e-5, complex128 <=
 1e-11), in place equals out of place, and the inverse reconstructs.  The
 reduced schedules (CM-CC-CM, LC, the IDFT route) run through the same
@@ -59,8 +61,15 @@ def test_resident_chain_matches_passes_and_oracle(torch, nl, N, count, precision
     x = torch.from_numpy(g).to(_dtype(torch, precision)).cuda()
     many = p.forward(x)
     torch.cuda.synchronize()
+    same_plan = precision == "c64" or N == 32
+
+    def agree(a, b):
+        if same_plan:
+            return torch.equal(a, b)
+        return chain.rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-13
+
     for b in sorted({0, count // 2, count - 1}):
-        assert torch.equal(_by_passes(p, torch, x[b].contiguous()), many[b]), f"image {b}"
+        assert agree(_by_passes(p, torch, x[b].contiguous()), many[b]), f"image {b}"
         assert chain.rel_l2(many[b].cpu().numpy(), chain.forward(po, g[b])) <= TOL[precision]
     y = x.clone()
     p.forward(y, out=y)
@@ -68,7 +77,7 @@ def test_resident_chain_matches_passes_and_oracle(torch, nl, N, count, precision
     back = p.inverse(many)
     assert chain.rel_l2(back.cpu().numpy(), g) <= TOL[precision]
     b = count - 1
-    assert torch.equal(_by_passes(p, torch, many[b].contiguous(), 1), back[b])
+    assert agree(_by_passes(p, torch, many[b].contiguous(), 1), back[b])
 
 
 def _cmccm_matrix(seed):
