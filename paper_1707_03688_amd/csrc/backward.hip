@@ -43,16 +43,16 @@ bool pair_size_ok(int n) { return pair_native_size(n) || (n >= 2 && n <= 2048 &&
 
 // Paired Bluestein pass (lines without a native plan).
 template <typename T, int M, bool COL, int LINES>
-__global__ void __launch_bounds__(LinePlan<M>::TPL* LINES) nslct_pair_bs_pass(PassArgs<T> a, BsArgs<T> bs) {
+__global__ void __launch_bounds__(BsPlan<M>::TPL* LINES) nslct_pair_bs_pass(PassArgs<T> a, BsArgs<T> bs) {
     __shared__ cplx<T> lds_all[LINES * lds_line_elems<M>()];
     const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     bs_body<T, M, COL, LINES, 2>(a, bs, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
 }
 template <typename T, int M, bool COL>
 hipError_t launch_pair_bs_m(const PassArgs<T>& a, const BsArgs<T>& bs, int count, hipStream_t s) {
-    constexpr int L = COL ? col_lines<T, M>() : row_lines<T, M>();
+    constexpr int L = bs_tile_lines<T, M, COL>();
     hipLaunchKernelGGL((nslct_pair_bs_pass<T, M, COL, L>), dim3((a.nlines + L - 1) / L, count),
-                       dim3(LinePlan<M>::TPL * L), 0, s, a, bs);
+                       dim3(BsPlan<M>::TPL * L), 0, s, a, bs);
     return hipGetLastError();
 }
 template <typename T, bool COL>

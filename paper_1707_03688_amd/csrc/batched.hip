@@ -85,7 +85,7 @@ bool batch_size_ok(int n) { return batch_native_size(n) || (n >= 2 && n <= 2048 
 // M-point line.
 template <typename T, int M, bool COL>
 constexpr int bs_lines() {
-    return COL ? col_lines<T, M>() : row_lines<T, M>();
+    return bs_tile_lines<T, M, COL>();
 }
 int host_bs_lines(int M, bool col, bool dbl) {
     switch (M) {
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__((width_lines<N, W, V>() * PlanVariant<N, V>::T
 // (all of one M): the same work list and grids as nslct_batched_pass, each
 // item through the single-image Bluestein body.
 template <typename T, int M, bool COL, bool LOOP>
-__global__ void __launch_bounds__((bs_lines<T, M, COL>() * LinePlan<M>::TPL))
+__global__ void __launch_bounds__((bs_lines<T, M, COL>() * BsPlan<M>::TPL))
     nslct_batched_bs_pass(BatchArgs<T> b, const BatchItem* __restrict__ items, const BatchPass<T>* __restrict__ passes,
                           BsArgs<T> bs) {
     constexpr int L = bs_lines<T, M, COL>();
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__((bs_lines<T, M, COL>() * LinePlan<M>::TPL))
 
 template <typename T, int M, bool COL>
 hipError_t launch_batched_bs_m(const BatchArgs<T>& a, const BsArgs<T>& bs, int grid, hipStream_t s) {
-    const dim3 block(bs_lines<T, M, COL>() * LinePlan<M>::TPL);
+    const dim3 block(bs_lines<T, M, COL>() * BsPlan<M>::TPL);
     if (grid >= a.nitems)
         hipLaunchKernelGGL((nslct_batched_bs_pass<T, M, COL, false>), dim3(a.nitems), block, 0, s, a, a.items,
                            a.passes, bs);

@@ -16,6 +16,22 @@
 namespace nslct {
 namespace {
 
+// Line plan of the M-point lines: the alternative split of a 256-point line
+// (8 samples on each of 32 threads instead of 16 on 16) is faster at every
+// size measured on gfx950 (one 100^2 complex64 image 65.4 -> 40.1 us,
+// complex128 105.9 -> 61.0; 75^2 59.1 -> 37.2), the other lengths' are
+// slower (128: 46.9 -> 69.4 us at 40^2; 512, 1024: about 2x).
+template <int M>
+using BsPlan = PlanVariant<M, (M == 256 ? 1 : 0)>;
+
+// Lines per tile of a Bluestein pass: row tiles of 256 threads, column
+// tiles with the thread count of the single-image column tile.
+template <typename T, int M, bool COL>
+constexpr int bs_tile_lines() {
+    constexpr int TPL = BsPlan<M>::TPL;
+    return COL ? (col_lines<T, M>() * LinePlan<M>::TPL + TPL - 1) / TPL : row_lines_of<BsPlan<M>>();
+}
+
 template <typename T>
 struct BsArgs {
     int N;               // line length
@@ -43,8 +59,8 @@ __device__ __forceinline__ cplx<double> bs_chirp(int r, int twoN, int S, double 
 template <typename T, int M, bool COL, int LINES, int NS = 1>
 __device__ __forceinline__ void bs_body(const PassArgs<T>& a, const BsArgs<T>& bs, int tile, size_t img_off,
                                         cplx<T>* lds_all) {
-    constexpr int TPL = LinePlan<M>::TPL;
-    using F = LineFFT<T, M, TPL>;
+    constexpr int TPL = BsPlan<M>::TPL;
+    using F = LineFFT<T, M, TPL, typename BsPlan<M>::L>;
     constexpr int E = F::E;
     constexpr int R0 = F::R0;
     constexpr int LL = lds_line_elems<M>();

@@ -401,7 +401,7 @@ namespace {
 // One Bluestein pass of a single-image launch: tile from the XCD-aware
 // order, image from blockIdx.y.
 template <typename T, int M, bool COL, int LINES>
-__global__ void __launch_bounds__(LinePlan<M>::TPL* LINES) nslct_bs_pass(PassArgs<T> a, BsArgs<T> bs) {
+__global__ void __launch_bounds__(BsPlan<M>::TPL* LINES) nslct_bs_pass(PassArgs<T> a, BsArgs<T> bs) {
     __shared__ cplx<T> lds_all[LINES * lds_line_elems<M>()];
     const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     bs_body<T, M, COL, LINES>(a, bs, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
@@ -409,10 +409,10 @@ __global__ void __launch_bounds__(LinePlan<M>::TPL* LINES) nslct_bs_pass(PassArg
 
 template <typename T, int M, bool COL>
 hipError_t launch_bs_t(const PassArgs<T>& a, const BsArgs<T>& b, int count, hipStream_t s) {
-    constexpr int L = COL ? col_lines<T, M>() : row_lines<T, M>();
+    constexpr int L = bs_tile_lines<T, M, COL>();
     static_assert(L * lds_line_elems<M>() * sizeof(cplx<T>) <= 160 * 1024, "LDS budget");
     hipLaunchKernelGGL((nslct_bs_pass<T, M, COL, L>), dim3((a.nlines + L - 1) / L, count),
-                       dim3(LinePlan<M>::TPL * L), 0, s, a, b);
+                       dim3(BsPlan<M>::TPL * L), 0, s, a, b);
     return hipGetLastError();
 }
 
