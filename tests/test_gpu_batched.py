@@ -141,6 +141,40 @@ def test_batched_c128(torch, nl):
         assert chain.rel_l2(got[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny), ref) <= 1e-11
 
 
+@pytest.mark.skip(reason="batches take native sides 64..1024 only: a build that added every native side "
+                         "from 2 to 2048 passed this test, but a later batch test in the same process then "
+                         "ended in a host segmentation fault whose cause was not found, so that build was "
+                         "withdrawn")
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_every_native_side_in_a_batch(torch, nl, precision):
+    """Native sides from 2 to 2048 (2^k and 3 * 2^k) batch together:
+    rectangular images pairing short and long sides, every image against the
+    FP64 oracle, graph and plain launches bitwise, the per-image loop to
+    rounding, and the inverse."""
+    shapes = [(2, 2048), (2048, 4), (6, 12), (8, 24), (16, 48), (32, 96), (12, 2), (24, 8), (48, 32),
+              (96, 16), (4, 6), (64, 2048)]
+    cands = synth.symplectic_candidates(53)
+    plans, oplans = [], []
+    for Nx, Ny in shapes:
+        d = (2 * np.pi / max(Nx, Ny)) ** 0.5
+        po = oplan.plan(next(cands), Nx, Ny, d, d)
+        plans.append(nl.Plan.from_stages(po.typ, po.mats, Nx, Ny, d, d, precision))
+        oplans.append(po)
+    b = nl.Batch(plans)
+    g = synth.complex_normal((b.total,), seed=9)
+    dt = torch.complex64 if precision == "c64" else torch.complex128
+    tol = 1e-5 if precision == "c64" else 1e-11
+    x = torch.from_numpy(g).to(dt).cuda()
+    out = b.forward(x)
+    assert torch.equal(out, b.run(x, mode=1))
+    assert _rel(out, b.run(x, mode=2)) <= (1e-6 if precision == "c64" else 1e-13)
+    got = out.cpu().numpy()
+    for o, p, po in zip(b.offsets, b.plans, oplans):
+        ref = chain.forward(po, g[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny))
+        assert chain.rel_l2(got[o:o + p.Nx * p.Ny].reshape(p.Nx, p.Ny), ref) <= tol, (p.Nx, p.Ny)
+    assert chain.rel_l2(b.inverse(out).cpu().numpy(), g) <= tol
+
+
 @pytest.mark.parametrize("precision", ["c64", "c128"])
 def test_bluestein_sizes_in_a_batch(torch, nl, precision):
     """Sides without a native line plan (Bluestein line DFTs) batch with the
