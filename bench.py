@@ -505,6 +505,23 @@ def main():
         p0.forward(x0s, out=y0s)
     torch.cuda.synchronize()
     c0_us = (time.perf_counter() - t0) / K * 1e6
+    # Many small images per call: 256 of 64 x 64 (complex64 and complex128),
+    # the whole chain per image in one launch from LDS.
+    many = {}
+    for prec in ("c64", "c128"):
+        pm = nl.Plan(M0, N0, N0, 1.0, 1.0, precision=prec)
+        xm = torch.from_numpy(synth.complex_normal((256, N0, N0), seed=1)).to(
+            torch.complex64 if prec == "c64" else torch.complex128).cuda()
+        ym = torch.empty_like(xm)
+        for _ in range(5):
+            pm.forward(xm, out=ym)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(50):
+            pm.forward(xm, out=ym)
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) / 50 * 1e6
+        many[prec] = {"us_per_call": us, "us_per_image": us / 256, "NsLCT_per_s": 256e6 / us}
     result = {
         "metric": METRIC,
         "value": value,
@@ -535,6 +552,7 @@ def main():
         "forward_inverse_rel_l2": recon,
         "small_64_c128": {"us_per_transform": c0_us, "NsLCT_per_s": 1e6 / c0_us,
                           "note": "64 x 64 complex128, unit spacing, one image per call"},
+        "small_64_many": {**many, "note": "256 images of 64 x 64 per call (one launch, images held in LDS)"},
     }
     if conc:
         result["concurrent8"] = {"value": conc, "unit": "NsLCT/s",
