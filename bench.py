@@ -60,8 +60,8 @@ def traffic_from_profile() -> dict:
     return {"rows": int(m.group(1)), "cols": int(m.group(2))}
 
 
-KERNEL_NAMES = {"rows": "nslct_pass<float, 1024, false, 4, false, 0> (passes 0, 2, 4: row lines)",
-                "cols": "nslct_pass<float, 1024, true, 4, false, 0> (passes 1, 3: column lines)"}
+KERNEL_NAMES = {"rows": "nslct_pass<float, 1024, false, 4, false, 0, true> (passes 0, 2, 4: row lines)",
+                "cols": "nslct_pass<float, 1024, true, 4, false, 0, true> (passes 1, 3: column lines)"}
 
 
 def draw_matrix(seed: int, N: int, d: float, nl):
@@ -542,7 +542,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profile().get(dom),
                      "kernel": KERNEL_NAMES[dom], "avg_launch_us": kern_ms[dom] * 1e3,
-                     "launches_per_transform": len(kernels[dom])},
+                     "launches_per_transform": len(kernels[dom]),
+                     "other_kernel": {k: {"kernel": KERNEL_NAMES[k], "avg_launch_us": kern_ms[k] * 1e3,
+                                          "achieved": bytes_per_launch / (kern_ms[k] * 1e-3) / 1e9,
+                                          "frac": bytes_per_launch / (kern_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                                          "traffic": traffic_from_profile().get(k)}
+                                      for k in kernels if k != dom}},
         "pass_us": [round(v * 1e3, 3) for v in pass_ms],
         "pass_us_back_to_back": [round(v * 1e3, 3) for v in loop_ms],
         "chain_us_events": chain_ms * 1e3,

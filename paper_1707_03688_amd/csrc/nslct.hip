@@ -77,13 +77,14 @@ int nslct::ensure_device_ready() {
 
 namespace {
 
-template <typename T, int N, bool COL, int LINES, bool X3, int V>
+template <typename T, int N, bool COL, int LINES, bool X3, int V, bool NT = false>
 __global__ void __launch_bounds__((PlanVariant<N, V>::TPL * LINES)) nslct_pass(PassArgs<T> a) {
     __shared__ cplx<T> lds_all[LINES * lds_line_elems<N>()];
     const int tile = COL ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    pass_body<T, N, COL, LINES, 1, X3, PlanVariant<N, V>>(a, tile, (size_t)blockIdx.y * a.img_stride, lds_all);
+    pass_body<T, N, COL, LINES, 1, X3, PlanVariant<N, V>, NT>(a, tile, (size_t)blockIdx.y * a.img_stride,
+                                                               lds_all);
 }
-template <typename T, int N, bool COL, bool X3, int V>
+template <typename T, int N, bool COL, bool X3, int V, bool NT = false>
 hipError_t launch_tv(const PassArgs<T>& a, int count, hipStream_t s) {
     constexpr int TPL = PlanVariant<N, V>::TPL;
     // Column tiles keep the thread count of the LinePlan tile; row tiles
@@ -92,7 +93,7 @@ hipError_t launch_tv(const PassArgs<T>& a, int count, hipStream_t s) {
     static_assert(L * lds_line_elems<N>() * sizeof(cplx<T>) <= 160 * 1024, "LDS budget");
     dim3 grid((a.nlines + L - 1) / L, count);
     dim3 block(TPL * L);
-    hipLaunchKernelGGL((nslct_pass<T, N, COL, L, X3, V>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((nslct_pass<T, N, COL, L, X3, V, NT>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 template <typename T, int N, bool COL, bool X3 = false>
@@ -105,6 +106,14 @@ hipError_t launch_t(const PassArgs<T>& a, int count, hipStream_t s) {
         if (alt) return launch_tv<T, N, COL, X3, 1>(a, count, s);
     }
     if constexpr (sizeof(T) == 8 && alt_plan_c128(N)) return launch_tv<T, N, COL, X3, 1>(a, count, s);
+    if constexpr (sizeof(T) == 4 && N == 1024 && !X3) {
+        // One 1024^2 complex64 image: streaming sample loads and stores leave
+        // less dirty data in the L2s for each pass's end to write back, which
+        // took the five-pass chain from 54.5 to 51.6 us on gfx950 (with more
+        // images per launch, where bandwidth rather than the pass boundaries
+        // sets the time, they were slower: 8 images 37 k -> 21 k NsLCT/s).
+        if (count == 1) return launch_tv<T, N, COL, X3, 0, true>(a, count, s);
+    }
     return launch_tv<T, N, COL, X3, 0>(a, count, s);
 }
 

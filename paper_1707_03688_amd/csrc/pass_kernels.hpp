@@ -131,6 +131,31 @@ __device__ __forceinline__ int store_to_fft(int p) {
     return i >= N ? i - N : i;
 }
 
+// Sample loads and stores of the passes; NT: non-temporal (streaming)
+// accesses of complex64 samples, which skip keeping the lines in the
+// caches (used where one image's pass is latency-bound, see launch_t).
+typedef float nslct_f2 __attribute__((ext_vector_type(2)));
+template <bool NT, typename T>
+__device__ __forceinline__ cplx<T> load_sample(const cplx<T>* p) {
+    if constexpr (NT && sizeof(T) == 4) {
+        const nslct_f2 u = __builtin_nontemporal_load(reinterpret_cast<const nslct_f2*>(p));
+        return {u.x, u.y};
+    } else {
+        return *p;
+    }
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void store_sample(cplx<T>* p, cplx<T> v) {
+    if constexpr (NT && sizeof(T) == 4) {
+        nslct_f2 u;
+        u.x = v.re;
+        u.y = v.im;
+        __builtin_nontemporal_store(u, reinterpret_cast<nslct_f2*>(p));
+    } else {
+        *p = v;
+    }
+}
+
 // One fused pass over LINES lines of length N per workgroup.  Row passes
 // (COL = false) read and write contiguous lines directly.  Column passes
 // cover a tile of LINES adjacent columns; their stores (and, for lines
@@ -138,7 +163,8 @@ __device__ __forceinline__ int store_to_fft(int p) {
 // global accesses cover LINES consecutive samples of each row (coalesced),
 // while each line's FFT work stays with the TPL threads that own it.
 // `img`, when given, replaces a.in and a.out (an image held in LDS).
-template <typename T, int N, bool COL, int LINES, int NS = 1, bool X3 = false, typename PP = LinePlan<N>>
+template <typename T, int N, bool COL, int LINES, int NS = 1, bool X3 = false, typename PP = LinePlan<N>,
+          bool NT = false>
 __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t img_off, cplx<T>* lds_all,
                                           cplx<T>* img = nullptr) {
     constexpr int TPL = PP::TPL;
@@ -182,7 +208,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
                 for (int r = 0; r < E; ++r) {
                     const int p = pos(r);
                     const int src = a.load_remap ? fft_to_store<N>(p) : p;
-                    v[sg][r] = in[(size_t)src * nl + line];
+                    v[sg][r] = load_sample<NT>(in + (size_t)src * nl + line);
                 }
             } else {
 #pragma unroll
@@ -197,7 +223,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
             for (int k = 0; k < E; ++k) {
                 const int p = u + TPL * k;
                 const int i = a.load_remap ? store_to_fft<N>(p) : p;
-                lds_all[c * LL + lds_pad(i)] = cok ? in[(size_t)p * nl + line0 + c] : cplx<T>{0, 0};
+                lds_all[c * LL + lds_pad(i)] = cok ? load_sample<NT>(in + (size_t)p * nl + line0 + c) : cplx<T>{0, 0};
             }
             __syncthreads();
 #pragma unroll
@@ -209,7 +235,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
                 for (int r = 0; r < E; ++r) {
                     const int p = pos(r);
                     const int src = a.load_remap ? fft_to_store<N>(p) : p;
-                    v[sg][r] = in[(size_t)line * N + src];
+                    v[sg][r] = load_sample<NT>(in + (size_t)line * N + src);
                 }
             } else {
 #pragma unroll
@@ -395,7 +421,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
                     const int p = u + TPL * k;
-                    out[(size_t)p * nl + line0 + c] = lds_all[c * LL + lds_pad(p)];
+                    store_sample<NT>(out + (size_t)p * nl + line0 + c, lds_all[c * LL + lds_pad(p)]);
                 }
             }
         } else if (active) {
@@ -403,7 +429,7 @@ __device__ __forceinline__ void pass_body(const PassArgs<T>& a, int tile, size_t
             for (int r = 0; r < E; ++r) {
                 const int p = pos(r);
                 const int dst = a.store_remap ? fft_to_store<N>(p) : p;
-                out[(size_t)line * N + dst] = v[sg][r];
+                store_sample<NT>(out + (size_t)line * N + dst, v[sg][r]);
             }
         }
     }
